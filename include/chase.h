@@ -1,0 +1,183 @@
+/*
+ * chase.h -- C ABI of the MI355X (gfx950) ChASE library.
+ *
+ * ChASE (Chebyshev Accelerated Subspace iteration Eigensolver) computes the
+ * nev lowest eigenpairs of a dense Hermitian (complex double) or symmetric
+ * (real double) matrix H by subspace iteration on nev+nex vectors
+ * (paper: Algorithm 1).  Each iteration filters the non-converged vectors
+ * with a Chebyshev polynomial (three-term recurrence of Eq. (3)),
+ * orthonormalises [locked | active] (QR), projects H onto the active part
+ * (Rayleigh-Ritz), computes residuals, locks converged pairs and re-optimises
+ * the per-vector polynomial degrees.
+ *
+ * Conventions shared by every entry point
+ *  - All matrices are column-major (LAPACK layout) with a leading dimension
+ *    (ld >= number of rows).  H is read in full (both triangles) and is never
+ *    modified; the caller guarantees it is Hermitian.
+ *  - Element type is fixed per handle: CHASE_C128 (interleaved re,im
+ *    doubles) or CHASE_F64.  "void*" device pointers point to that type.
+ *  - Pointers named *_dev are device (HBM) pointers owned by the caller;
+ *    *_host are host pointers owned by the caller.  The library owns only the
+ *    workspace inside the handle, allocated once in chase_create.
+ *  - Every call is ordered on the given HIP stream (0 = null stream) and
+ *    returns only after the results it writes to host memory are valid;
+ *    device outputs are valid once the stream reaches the end of the call
+ *    (the calls below synchronise the stream before returning).
+ *  - Errors: a chase_status is returned; no exception crosses the ABI.  The
+ *    message of the last error on the calling thread is available from
+ *    chase_last_error().  On any error other than CHASE_ERR_NOCONV the
+ *    outputs are unspecified.
+ *  - A handle may be used by one thread at a time.
+ */
+#ifndef CHASE_MI355X_H
+#define CHASE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum chase_status {
+  CHASE_OK = 0,
+  CHASE_ERR_ARG = 1,      /* invalid argument (sizes, pointers, options)   */
+  CHASE_ERR_NOMEM = 2,    /* workspace does not fit in free device memory  */
+  CHASE_ERR_HIP = 3,      /* a HIP / rocSOLVER runtime call failed          */
+  CHASE_ERR_NOCONV = 4,   /* max_iter reached; outputs hold the best pairs */
+  CHASE_ERR_NUMERIC = 5   /* NaN/Inf or breakdown of every QR variant      */
+} chase_status;
+
+typedef enum chase_dtype { CHASE_C128 = 0, CHASE_F64 = 1 } chase_dtype;
+
+/* Precision of the filter's matrix products (the rest of the method always
+ * runs in FP64).  CHASE_PREC_FP32: complex64/float32 MFMA products with FP32
+ * accumulation; a vector switches to FP64 once its residual is below
+ * switch_tol (and stays there). */
+typedef enum chase_prec { CHASE_PREC_FP64 = 0, CHASE_PREC_FP32 = 1 } chase_prec;
+
+typedef struct chase_opts {
+  int max_deg;         /* cap of the optimised degree (default 36)           */
+  int deg_extra;       /* margin added to the optimised degree (default 2)   */
+  int optimize_degree; /* 1: per-vector degrees (Algorithm 1); 0: fixed deg   */
+  int lanczos_steps;   /* length of each Lanczos run (default 25)            */
+  int lanczos_vecs;    /* number of Lanczos runs, 1..8 (default 4)           */
+  int max_iter;        /* subspace iterations before NOCONV (default 50)     */
+  int filter_prec;     /* chase_prec (default CHASE_PREC_FP64)                */
+  double switch_tol;   /* low->FP64 switch residual; <=0: 3e-6 for FP32      */
+  int verbose;         /* 1: one line per iteration on stderr                */
+  int reserved[7];
+} chase_opts;
+
+typedef struct chase_stats {
+  int iterations;        /* subspace iterations performed                    */
+  int locked;            /* converged (locked) pairs                         */
+  int64_t matvecs_fp64;  /* filter matrix-vector products in FP64 (Matvecs)  */
+  int64_t matvecs_low;   /* filter matrix-vector products in low precision   */
+  double t_all;          /* seconds, whole solve (Table 2 columns)           */
+  double t_lanczos, t_filter, t_qr, t_rr, t_resid;
+  double t_filter_kernels; /* summed HIP-event time of the filter GEMMs       */
+  int64_t filter_launches; /* number of filter GEMM launches                 */
+  double filter_flops;     /* algorithmic filter FLOPs (8 n^2 per complex mv) */
+  double b_sup, mu_1, mu_ne; /* final spectral bounds                         */
+  int qr_shifted;          /* QR passes that needed the shifted variant      */
+  int qr_householder;      /* QR calls that fell back to Householder         */
+} chase_stats;
+
+typedef struct chase_handle_s* chase_handle_t;
+
+/* Fill *opts with the defaults listed above. */
+void chase_default_opts(chase_opts* opts);
+
+/* Bytes of device workspace chase_create allocates for this problem
+ * (one-GPU form of the paper's GPU memory estimate, Eq. (7), without the
+ * caller-owned matrix).  Returns 0 for invalid sizes. */
+size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex,
+                             const chase_opts* opts);
+
+/* Create a handle on the current HIP device and allocate its workspace
+ * once (as the paper pre-allocates its library buffers, Section 2.3).
+ * Requires 1 <= nev, 1 <= nex, nev+nex <= n.  opts may be NULL (defaults).
+ * CHASE_ERR_NOMEM if the workspace exceeds the free device memory. */
+chase_status chase_create(chase_handle_t* handle, chase_dtype dtype, int64_t n,
+                          int nev, int nex, const chase_opts* opts);
+void chase_destroy(chase_handle_t handle);
+
+/* Algorithm 1.  Inputs: H_dev (n x n, ld ldh), tol > 0 (residual bound
+ * relative to max(|mu_1|,|b_sup|) of the Lanczos bounds), degree >= 2
+ * (initial degree, rounded up to even), V0_dev (n x (nev+nex), ld n: the
+ * start block), S_dev (n x lanczos_vecs, ld n: Lanczos start vectors).
+ * Outputs: evals_host[nev] ascending, evecs_dev (n x nev, ld ldv),
+ * resid_host[nev] (may be NULL), stats (may be NULL).
+ * CHASE_ERR_NOCONV: max_iter reached; outputs hold the lowest nev current
+ * Ritz pairs and stats->locked tells how many converged. */
+chase_status chase_solve(chase_handle_t handle, const void* H_dev, int64_t ldh,
+                         double tol, int degree, const void* V0_dev,
+                         const void* S_dev, double* evals_host, void* evecs_dev,
+                         int64_t ldv, double* resid_host, chase_stats* stats,
+                         void* stream);
+
+/* Spectral bounds by the Lanczos step of Algorithm 1 from the start vectors
+ * S_dev (n x nvec, ld n, nvec <= lanczos_vecs) with `steps` steps each:
+ * b_sup (upper bound of the spectrum), mu_1 (lowest Ritz value) and mu_ne
+ * (DoS estimate of the (nev+nex)-th eigenvalue).  alpha_host/beta_host
+ * (may be NULL) receive the tridiagonal entries, nvec x steps, run-major;
+ * steps_host[nvec] (may be NULL) the length of each run. */
+chase_status chase_lanczos(chase_handle_t handle, const void* H_dev, int64_t ldh,
+                           const void* S_dev, int nvec, int steps, double* b_sup,
+                           double* mu_1, double* mu_ne, double* alpha_host,
+                           double* beta_host, int* steps_host, void* stream);
+
+/* Chebyshev filter (Eq. (3), scaled so the polynomial is 1 at mu_1, damping
+ * [mu_ne, b_sup]).  Column a of X_dev (n x k, ld ldx, in/out) is replaced by
+ * p_{m_a}(H) x_a with m_a = degrees_host[a]: even, >= 2, non-decreasing in a.
+ * prec: chase_prec.  record_tape=1 keeps every intermediate block on the
+ * device for chase_filter_adjoint (needs tape memory; CHASE_ERR_NOMEM if it
+ * does not fit).  matvecs (may be NULL) receives the matrix-vector count. */
+chase_status chase_filter(chase_handle_t handle, const void* H_dev, int64_t ldh,
+                          void* X_dev, int64_t ldx, int k, const int* degrees_host,
+                          double b_sup, double mu_1, double mu_ne, int prec,
+                          int record_tape, int64_t* matvecs, void* stream);
+
+/* QR step of Algorithm 1: orthonormalise the n x k block X_dev (ld ldx)
+ * in place, keeping its first `locked` columns (assumed orthonormal)
+ * unchanged; the others become orthonormal and orthogonal to them with the
+ * same span as [locked | rest]. */
+chase_status chase_qr(chase_handle_t handle, void* X_dev, int64_t ldx, int k,
+                      int locked, void* stream);
+
+/* Rayleigh-Ritz + residual steps of Algorithm 1 on the orthonormal block
+ * Q_dev (n x k, ld ldq, in/out): Q is replaced by the Ritz vectors,
+ * ritz_host[k] receives the Ritz values ascending and resid_host[k]
+ * (may be NULL) ||H v - theta v||_2 / norm_scale. */
+chase_status chase_rayleigh_ritz(chase_handle_t handle, const void* H_dev,
+                                 int64_t ldh, void* Q_dev, int64_t ldq, int k,
+                                 double norm_scale, double* ritz_host,
+                                 double* resid_host, void* stream);
+
+/* Adjoint of the eigenvalue map: dH += V diag(g) V^H for V_dev (n x m,
+ * ld ldv) orthonormal eigenvectors and g_host[m]; dH_dev (n x n, ld ldd)
+ * is accumulated into (the gradient of sum_i g_i lambda_i w.r.t. Hermitian
+ * H, torch's complex convention). */
+chase_status chase_eigval_adjoint(chase_handle_t handle, const void* V_dev,
+                                  int64_t ldv, int m, const double* g_host,
+                                  void* dH_dev, int64_t ldd, void* stream);
+
+/* Adjoint of the last chase_filter call made with record_tape=1: given
+ * gY_dev (n x k, ld ldg), the gradient of a real loss w.r.t. the filtered
+ * block, accumulate into dH_dev (n x n, ld ldd) the gradient w.r.t. H
+ * (recurrence replayed in reverse, rank-k updates, Hermitian part) and, if
+ * gX_dev is not NULL, write the gradient w.r.t. the filter input (n x k,
+ * ld ldg).  Degrees and bounds are those of the recorded call. */
+chase_status chase_filter_adjoint(chase_handle_t handle, const void* H_dev,
+                                  int64_t ldh, const void* gY_dev, int64_t ldg,
+                                  void* dH_dev, int64_t ldd, void* gX_dev,
+                                  void* stream);
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char* chase_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHASE_MI355X_H */

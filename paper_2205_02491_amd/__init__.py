@@ -1,0 +1,334 @@
+"""Python binding of the MI355X ChASE library (libchase.so, C ABI in
+include/chase.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Torch tensors provide device memory and streams.
+
+Layout: torch tensors are row-major, the library is column-major.  The
+column-major reading of a row-major Hermitian H is conj(H), which has the
+same eigenvalues and conjugated eigenvectors, so vectors are passed and
+returned conjugate-transposed (``X.mH``) and H is passed as is, without a
+copy.  Gradients w.r.t. H come back directly in torch's convention.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libchase.so")
+
+C128, F64 = 0, 1
+PREC_FP64, PREC_FP32 = 0, 1
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC = range(6)
+_STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
+           4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}
+
+EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
+            "chase_solve", "chase_lanczos", "chase_filter", "chase_qr",
+            "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_filter_adjoint",
+            "chase_last_error"]
+
+
+class ChaseError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("max_deg", ctypes.c_int), ("deg_extra", ctypes.c_int),
+                ("optimize_degree", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
+                ("lanczos_vecs", ctypes.c_int), ("max_iter", ctypes.c_int),
+                ("filter_prec", ctypes.c_int), ("switch_tol", ctypes.c_double),
+                ("verbose", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int), ("locked", ctypes.c_int),
+                ("matvecs_fp64", ctypes.c_int64), ("matvecs_low", ctypes.c_int64),
+                ("t_all", ctypes.c_double), ("t_lanczos", ctypes.c_double),
+                ("t_filter", ctypes.c_double), ("t_qr", ctypes.c_double),
+                ("t_rr", ctypes.c_double), ("t_resid", ctypes.c_double),
+                ("t_filter_kernels", ctypes.c_double), ("filter_launches", ctypes.c_int64),
+                ("filter_flops", ctypes.c_double), ("b_sup", ctypes.c_double),
+                ("mu_1", ctypes.c_double), ("mu_ne", ctypes.c_double),
+                ("qr_shifted", ctypes.c_int), ("qr_householder", ctypes.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libchase.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2205_02491_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, ci, cd = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_double
+    pd, pi, pi64 = ctypes.POINTER(cd), ctypes.POINTER(ci), ctypes.POINTER(i64)
+    L.chase_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.chase_default_opts.restype = None
+    L.chase_workspace_bytes.argtypes = [ci, i64, ci, ci, ctypes.POINTER(Opts)]
+    L.chase_workspace_bytes.restype = ctypes.c_size_t
+    L.chase_create.argtypes = [ctypes.POINTER(vp), ci, i64, ci, ci, ctypes.POINTER(Opts)]
+    L.chase_create.restype = ci
+    L.chase_destroy.argtypes = [vp]
+    L.chase_destroy.restype = None
+    L.chase_solve.argtypes = [vp, vp, i64, cd, ci, vp, vp, pd, vp, i64, pd,
+                              ctypes.POINTER(Stats), vp]
+    L.chase_solve.restype = ci
+    L.chase_lanczos.argtypes = [vp, vp, i64, vp, ci, ci, pd, pd, pd, pd, pd, pi, vp]
+    L.chase_lanczos.restype = ci
+    L.chase_filter.argtypes = [vp, vp, i64, vp, i64, ci, pi, cd, cd, cd, ci, ci, pi64, vp]
+    L.chase_filter.restype = ci
+    L.chase_qr.argtypes = [vp, vp, i64, ci, ci, vp]
+    L.chase_qr.restype = ci
+    L.chase_rayleigh_ritz.argtypes = [vp, vp, i64, vp, i64, ci, cd, pd, pd, vp]
+    L.chase_rayleigh_ritz.restype = ci
+    L.chase_eigval_adjoint.argtypes = [vp, vp, i64, ci, pd, vp, i64, vp]
+    L.chase_eigval_adjoint.restype = ci
+    L.chase_filter_adjoint.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
+    L.chase_filter_adjoint.restype = ci
+    L.chase_last_error.argtypes = []
+    L.chase_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status, allow_noconv=False):
+    if status == OK or (allow_noconv and status == ERR_NOCONV):
+        return status
+    raise ChaseError(status, lib().chase_last_error().decode())
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().chase_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def chase_workspace_bytes(n, nev, nex, cplx=True, opts: Opts | None = None) -> int:
+    return int(lib().chase_workspace_bytes(C128 if cplx else F64, n, nev, nex,
+                                           ctypes.byref(opts) if opts else None))
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.complex128:
+        return C128
+    if t.dtype == torch.float64:
+        return F64
+    raise TypeError(f"unsupported dtype {t.dtype}: complex128 or float64")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t):
+    if not t.is_cuda:
+        raise ValueError("tensor must be on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _colmajor(x):
+    """Column-major buffer (as a row-major (k, n) tensor) of the vectors of x
+    (n, k) in the conj(H) frame: x.mH, contiguous."""
+    return x.mH.contiguous()
+
+
+class Handle:
+    """Owns the library handle and its device workspace (allocated once)."""
+
+    def __init__(self, n, nev, nex, dtype=None, opts: Opts | None = None, **kw):
+        import torch
+        dtype = dtype or torch.complex128
+        self.cplx = dtype == torch.complex128
+        self.n, self.nev, self.nex = int(n), int(nev), int(nex)
+        self.opts = opts or default_opts(**kw)
+        self.dtype = dtype
+        h = ctypes.c_void_p()
+        _check(lib().chase_create(ctypes.byref(h), C128 if self.cplx else F64, self.n,
+                                  self.nev, self.nex, ctypes.byref(self.opts)))
+        self._h = h
+
+    @property
+    def ptr(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().chase_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def _ensure_handle(handle, H, nev, nex, opts):
+    if handle is not None:
+        return handle, False
+    return Handle(H.shape[0], nev, nex, H.dtype, opts), True
+
+
+def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, handle=None,
+                seed=0):
+    """Lowest nev eigenpairs of the Hermitian H (n x n torch tensor on the GPU,
+    complex128 or float64).  V0 (n x (nev+nex)) and S (n x lanczos_vecs) are
+    the start block and the Lanczos start vectors (drawn from a seeded normal
+    distribution when omitted).  Returns (evals numpy[nev], evecs tensor
+    (n, nev), resid numpy[nev], stats dict).  NOCONV returns the best pairs
+    with stats['converged'] = False."""
+    import torch
+    n = H.shape[0]
+    assert H.shape == (n, n) and H.is_contiguous()
+    _dtype_code(H)
+    h, own = _ensure_handle(handle, H, nev, nex, opts)
+    try:
+        ne = nev + nex
+        nl = h.opts.lanczos_vecs
+        if V0 is None or S is None:
+            g = torch.Generator(device=H.device)
+            g.manual_seed(seed)
+            if V0 is None:
+                V0 = torch.randn((n, ne), generator=g, dtype=H.dtype, device=H.device)
+            if S is None:
+                S = torch.randn((n, nl), generator=g, dtype=H.dtype, device=H.device)
+        v0c = _colmajor(V0.to(H.dtype))
+        sc = _colmajor(S.to(H.dtype))
+        evecs_buf = torch.empty((nev, n), dtype=H.dtype, device=H.device)
+        ev = np.zeros(nev)
+        rs = np.zeros(nev)
+        st = Stats()
+        status = lib().chase_solve(h.ptr, _dev(H), n, float(tol), int(degree), _dev(v0c),
+                                   _dev(sc), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   _dev(evecs_buf), n,
+                                   rs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                   ctypes.byref(st), _stream())
+        _check(status, allow_noconv=True)
+        d = st.as_dict()
+        d["converged"] = status == OK
+        return ev, evecs_buf.mH, rs, d
+    finally:
+        if own:
+            h.close()
+
+
+def chase_lanczos(H, S, steps=None, handle=None, n_e=None, opts=None):
+    """Lanczos bounds from the start vectors S (n x nvec).  Returns
+    (b_sup, mu_1, mu_ne, alpha[nvec, steps], beta[nvec, steps], lengths)."""
+    n = H.shape[0]
+    nvec = S.shape[1]
+    if handle is None:
+        assert n_e is not None
+        nev = max(1, n_e // 2)
+        handle = Handle(n, nev, n_e - nev, H.dtype, opts)
+    steps = steps or handle.opts.lanczos_steps
+    sc = _colmajor(S.to(H.dtype))
+    a = np.zeros((nvec, steps))
+    b = np.zeros((nvec, steps))
+    lens = np.zeros(nvec, dtype=np.int32)
+    out = [ctypes.c_double() for _ in range(3)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(lib().chase_lanczos(handle.ptr, _dev(H), n, _dev(sc), nvec, steps,
+                               ctypes.byref(out[0]), ctypes.byref(out[1]), ctypes.byref(out[2]),
+                               a.ctypes.data_as(pd), b.ctypes.data_as(pd),
+                               lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _stream()))
+    return out[0].value, out[1].value, out[2].value, a, b, lens
+
+
+def chase_filter(H, X, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64, record_tape=False,
+                 handle=None):
+    """Chebyshev filter of the columns of X (n x k) with per-column even,
+    non-decreasing degrees.  Returns (Y, matvecs); X is not modified."""
+    import torch
+    n, k = X.shape
+    if handle is None:
+        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1 if k > 1 else 1, H.dtype)
+    buf = _colmajor(X.to(H.dtype))
+    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    mv = ctypes.c_int64()
+    _check(lib().chase_filter(handle.ptr, _dev(H), n, _dev(buf), n, k,
+                              deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(b_sup),
+                              float(mu_1), float(mu_ne), int(prec), int(bool(record_tape)),
+                              ctypes.byref(mv), _stream()))
+    return buf.mH, mv.value
+
+
+def chase_qr(X, locked=0, handle=None):
+    """Orthonormalise X (n x k) keeping its first `locked` columns."""
+    n, k = X.shape
+    if handle is None:
+        handle = Handle(n, max(1, k - 1), 1, X.dtype)
+    buf = _colmajor(X)
+    _check(lib().chase_qr(handle.ptr, _dev(buf), n, k, int(locked), _stream()))
+    return buf.mH
+
+
+def chase_rayleigh_ritz(H, Q, norm_scale=1.0, handle=None):
+    """Rayleigh-Ritz + residuals on the orthonormal Q (n x k): returns
+    (ritz numpy[k], V tensor (n, k), resid numpy[k])."""
+    n, k = Q.shape
+    if handle is None:
+        handle = Handle(n, max(1, k - 1), 1, H.dtype)
+    buf = _colmajor(Q.to(H.dtype))
+    ritz = np.zeros(k)
+    res = np.zeros(k)
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(lib().chase_rayleigh_ritz(handle.ptr, _dev(H), n, _dev(buf), n, k, float(norm_scale),
+                                     ritz.ctypes.data_as(pd), res.ctypes.data_as(pd), _stream()))
+    return ritz, buf.mH, res
+
+
+def chase_eigval_adjoint(V, g, dH, handle=None):
+    """dH += V diag(g) V^H (in place on the torch tensor dH, n x n)."""
+    n, m = V.shape
+    if handle is None:
+        handle = Handle(n, max(1, m - 1) if m > 1 else 1, 1, V.dtype)
+    buf = _colmajor(V)
+    gg = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    _check(lib().chase_eigval_adjoint(handle.ptr, _dev(buf), n, m,
+                                      gg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _dev(dH), n, _stream()))
+    return dH
+
+
+def chase_filter_adjoint(H, gY, dH, handle, want_gX=False):
+    """Adjoint of the last recorded chase_filter on `handle`: dH += dL/dH;
+    returns dL/dX0 (n x k) if want_gX."""
+    import torch
+    n, k = gY.shape
+    gbuf = _colmajor(gY.to(H.dtype))
+    gx = torch.empty_like(gbuf) if want_gX else None
+    _check(lib().chase_filter_adjoint(handle.ptr, _dev(H), n, _dev(gbuf), n, _dev(dH), n,
+                                      _dev(gx) if gx is not None else None, _stream()))
+    return gx.mH if gx is not None else None
+
+
+from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
+
+__all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
+           "chase_solve", "chase_lanczos", "chase_filter", "chase_qr", "chase_rayleigh_ritz",
+           "chase_eigval_adjoint", "chase_filter_adjoint", "ChaseEigh", "chase_eigh",
+           "filtered_block", "lib", "EXPORTED"]

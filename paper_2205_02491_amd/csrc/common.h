@@ -1,0 +1,133 @@
+// Internal declarations shared by the ChASE HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+
+#include "../../include/chase.h"
+
+namespace chase {
+
+struct Error : std::runtime_error {
+  chase_status status;
+  Error(chase_status s, const std::string& m) : std::runtime_error(m), status(s) {}
+};
+
+#define CHASE_HIP(call)                                                            \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      throw ::chase::Error(CHASE_ERR_HIP, std::string(#call) + ": " +              \
+                                              hipGetErrorString(e_));              \
+  } while (0)
+
+#define CHASE_REQUIRE(cond, msg)                                                   \
+  do {                                                                             \
+    if (!(cond)) throw ::chase::Error(CHASE_ERR_ARG, msg);                         \
+  } while (0)
+
+struct c128 {
+  double re, im;
+};
+struct c64 {
+  float re, im;
+};
+
+// ------------------------------------------------------------------ GEMM
+// Operand forms: N = as stored (column-major), C = conjugate transpose
+// (transpose for real data).
+enum Op { OP_N = 0, OP_C = 1 };
+
+// Epilogues of the tile GEMM C = op(A) op(B):
+//   STORE : C = alpha*AB + beta*C
+//   CHEB  : out = alpha*(AB - gamma*Xs) + beta*out   (one Chebyshev step;
+//           Xs is the B operand itself, out may hold X_{s-2})
+//   SPLITK: partial sums of a K-slice to a workspace (reduced separately)
+//   RESID : partial column sums of |AB - lambda_j * V|^2 per row tile
+enum Epi { EPI_STORE = 0, EPI_CHEB = 1, EPI_SPLITK = 2, EPI_RESID = 3 };
+
+// Arithmetic of the products: FP64 (double MFMA) or FP32 (float MFMA,
+// operands rounded to float when staged in LDS, FP32 accumulation).
+enum Prec { PREC_F64 = 0, PREC_F32 = 1 };
+
+struct GemmArgs {
+  int64_t M, N, K;
+  const void* A;  // element type: c128/double, or c64/float when a_f32
+  int64_t lda;
+  const void* B;
+  int64_t ldb;
+  void* C;  // output (STORE/CHEB: same element type as B; SPLITK: ws)
+  int64_t ldc;
+  double alpha, beta, gamma;
+  const double* lambda;  // RESID: per-column shift (device)
+  const void* V;         // RESID: matrix subtracted (ld ldv)
+  int64_t ldv;
+  double* partial;       // RESID: [row_tiles][N] partial sums
+  int splits;            // SPLITK: number of K slices (grid z)
+  int64_t kslice;        // SPLITK: K length per slice (multiple of the K tile)
+  int a_f32;             // A stored as c64/float (mixed-precision copy of H)
+};
+
+// Launch the tile GEMM. cplx selects complex (c128) vs real (double) data.
+void gemm(bool cplx, Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g,
+          hipStream_t st);
+int gemm_row_tiles(int64_t M);
+// Split-K plan for an M x N result with long K: number of slices and the
+// per-slice K length; workspace elements needed = splits * M * N.
+void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice);
+
+// ------------------------------------------------------------------ misc kernels
+void fill_zero(void* p, int64_t bytes, hipStream_t st);
+void copy_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
+               int64_t k, hipStream_t st);
+void gather_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
+                 int64_t k, const int* perm_dev, hipStream_t st);
+// sum the split-K slices ws[z][i + j*M] into C (ld ldc); herm: C=(S+S^H)/2
+void splitk_reduce(bool cplx, const void* ws, int splits, int64_t M, int64_t N, void* C,
+                   int64_t ldc, bool herm, hipStream_t st);
+// Gram post-processing for Cholesky QR: d_j = 1/sqrt(S_jj); S = D S D + shift*I;
+// flags[0] set to 1 if some S_jj <= 0 or is not finite.
+void gram_scale(bool cplx, void* S, int64_t lds, int64_t k, double shift, double* d,
+                int* flags, hipStream_t st);
+// M = D * triu(Rinv): scale row i by d_i, zero the strictly lower part.
+void triu_rowscale(bool cplx, void* R, int64_t ldr, int64_t k, const double* d,
+                   hipStream_t st);
+void diag_real(bool cplx, const void* A, int64_t lda, int64_t k, double* out,
+               hipStream_t st);
+// res[j] = sqrt(sum_t partial[t][j]) * inv_scale
+void resid_finish(const double* partial, int tiles, int64_t N, double inv_scale, double* res,
+                  hipStream_t st);
+// V = V * diag(g) (columns scaled by real g)
+void scale_cols(bool cplx, void* V, int64_t ldv, int64_t n, int64_t k, const double* g,
+                hipStream_t st);
+// Y += a * X for n x k blocks
+void axpy_cols(bool cplx, double a, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t n,
+               int64_t k, hipStream_t st);
+// Hermitian part in place: A = (A + A^H)/2 (n x n)
+void herm_part(bool cplx, void* A, int64_t lda, int64_t n, hipStream_t st);
+// c128 -> c64 (or double -> float) conversion of an n x n matrix into ld n
+void to_f32(bool cplx, const void* src, int64_t lds, void* dst, int64_t n, hipStream_t st);
+// flags[0] |= 1 if any entry of the n x k block is not finite
+void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, int* flags,
+                  hipStream_t st);
+
+// ------------------------------------------------------------------ Lanczos
+struct LanczosBufs {
+  void* q_prev;    // n x nv
+  void* q_cur;     // n x nv
+  void* w;         // n x nv
+  void* wpart;     // splits x nv x n
+  double* dotp;    // blocks x nv
+  double* nrmp;    // blocks x nv
+  double* alpha;   // steps x nv
+  double* beta;    // steps x nv
+  int max_splits;
+};
+void lanczos_run(bool cplx, const void* H, int64_t ldh, int64_t n, const void* S, int nv,
+                 int steps, LanczosBufs& b, hipStream_t st);
+size_t lanczos_bytes(bool cplx, int64_t n, int nv, int steps, int* max_splits);
+
+}  // namespace chase

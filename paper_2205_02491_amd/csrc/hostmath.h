@@ -1,0 +1,32 @@
+// Host-side scalar logic of Algorithm 1 (see hostmath.cpp).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "../../include/chase.h"
+
+namespace chase {
+
+struct Bounds {
+  double b_sup, mu_1, mu_ne;
+};
+
+// One step of Eq. (3): X_s = alpha (H - gamma I) X_{s-1} + beta X_{s-2}.
+struct Coef {
+  double alpha, gamma, beta;
+};
+
+void sym_eig_small(std::vector<double> a, int k, std::vector<double>& val,
+                   std::vector<double>& vec);
+
+// alpha/beta are steps x nv, step-major (entry j*nv + r)
+Bounds lanczos_bounds(const std::vector<double>& alpha, const std::vector<double>& beta, int nv,
+                      int steps, int64_t n, int n_e, std::vector<int>* run_len);
+
+std::vector<Coef> cheb_coefficients(int m, double b_sup, double mu_1, double mu_ne);
+
+int optimal_degree(double res, double ritz, double c, double e, double tol, const chase_opts& o,
+                   int deg);
+
+}  // namespace chase

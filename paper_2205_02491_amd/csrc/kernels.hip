@@ -1,0 +1,642 @@
+// Bandwidth-bound helper kernels of the ChASE hot path: block copies and
+// column gathers (the degree sort of Algorithm 1), split-K reductions,
+// Cholesky-QR scaling, residual-norm finishing, and the Lanczos block
+// matrix-vector product with its wavefront reductions.
+#include "common.h"
+
+#include <algorithm>
+#include <utility>
+
+namespace chase {
+namespace {
+
+typedef double d2v __attribute__((ext_vector_type(2)));
+
+constexpr int TPB = 256;
+
+inline int blocks_for(int64_t work, int per_block, int cap = 65535 * 8) {
+  int64_t b = (work + per_block - 1) / per_block;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return (int)b;
+}
+
+__global__ void fill_zero_k(uint32_t* p, int64_t words) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < words;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0u;
+}
+__global__ void fill_zero_bytes_k(unsigned char* p, int64_t bytes) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < bytes;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// one scalar = double; complex elements are 2 scalars (w = 2)
+template <int W>
+__global__ void copy_cols_k(const double* __restrict__ src, int64_t lds, double* __restrict__ dst,
+                            int64_t ldd, int64_t n, int64_t k, const int* __restrict__ perm) {
+  const int64_t rows = n * W;
+  for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
+    const int64_t sj = perm ? perm[j] : j;
+    const double* s = src + sj * lds * W;
+    double* d = dst + j * ldd * W;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows;
+         i += (int64_t)gridDim.x * blockDim.x)
+      d[i] = s[i];
+  }
+}
+
+template <bool CPLX>
+__global__ void splitk_reduce_k(const double* __restrict__ ws, int splits, int64_t M, int64_t N,
+                                double* __restrict__ C, int64_t ldc, bool herm) {
+  const int64_t total = M * N;
+  const int W = CPLX ? 2 : 1;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % M, j = e / M;
+    double sr = 0, si = 0;
+    for (int z = 0; z < splits; ++z) {
+      sr += ws[(z * total + e) * W];
+      if (CPLX) si += ws[(z * total + e) * W + 1];
+    }
+    if (herm) {
+      // (S + S^H)/2 at (i, j): needs S(j, i) as well
+      const int64_t et = j + i * M;
+      double tr = 0, ti = 0;
+      for (int z = 0; z < splits; ++z) {
+        tr += ws[(z * total + et) * W];
+        if (CPLX) ti += ws[(z * total + et) * W + 1];
+      }
+      sr = 0.5 * (sr + tr);
+      si = 0.5 * (si - ti);
+    }
+    C[(i + j * ldc) * W] = sr;
+    if (CPLX) C[(i + j * ldc) * W + 1] = si;
+  }
+}
+
+template <bool CPLX>
+__global__ void gram_diag_k(const double* __restrict__ S, int64_t lds, int64_t k, double* d,
+                            int* flags) {
+  const int W = CPLX ? 2 : 1;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < k;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const double s = S[(j + j * lds) * W];
+    if (!(s > 0.0) || !isfinite(s)) {
+      flags[0] = 1;
+      d[j] = 1.0;
+    } else {
+      d[j] = 1.0 / sqrt(s);
+    }
+  }
+}
+
+template <bool CPLX>
+__global__ void gram_apply_k(double* __restrict__ S, int64_t lds, int64_t k,
+                             const double* __restrict__ d, double shift) {
+  const int W = CPLX ? 2 : 1;
+  const int64_t total = k * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % k, j = e / k;
+    const double f = d[i] * d[j];
+    double* p = S + (i + j * lds) * W;
+    p[0] *= f;
+    if (CPLX) p[1] *= f;
+    if (i == j) {
+      p[0] += shift;
+      if (CPLX) p[1] = 0.0;
+    }
+  }
+}
+
+template <bool CPLX>
+__global__ void triu_rowscale_k(double* __restrict__ R, int64_t ldr, int64_t k,
+                                const double* __restrict__ d) {
+  const int W = CPLX ? 2 : 1;
+  const int64_t total = k * k;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % k, j = e / k;
+    double* p = R + (i + j * ldr) * W;
+    if (i > j) {
+      p[0] = 0.0;
+      if (CPLX) p[1] = 0.0;
+    } else {
+      p[0] *= d[i];
+      if (CPLX) p[1] *= d[i];
+    }
+  }
+}
+
+template <bool CPLX>
+__global__ void diag_real_k(const double* __restrict__ A, int64_t lda, int64_t k, double* out) {
+  const int W = CPLX ? 2 : 1;
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < k;
+       j += (int64_t)gridDim.x * blockDim.x)
+    out[j] = A[(j + j * lda) * W];
+}
+
+__global__ void resid_finish_k(const double* __restrict__ partial, int tiles, int64_t N,
+                               double inv_scale, double* __restrict__ res) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < N;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0;
+    for (int t = 0; t < tiles; ++t) s += partial[(int64_t)t * N + j];
+    res[j] = sqrt(s) * inv_scale;
+  }
+}
+
+template <bool CPLX>
+__global__ void scale_cols_k(double* __restrict__ V, int64_t ldv, int64_t n, int64_t k,
+                             const double* __restrict__ g) {
+  const int W = CPLX ? 2 : 1;
+  for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
+    const double f = g[j];
+    double* c = V + j * ldv * W;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * W;
+         i += (int64_t)gridDim.x * blockDim.x)
+      c[i] *= f;
+  }
+}
+
+template <int W>
+__global__ void axpy_cols_k(double a, const double* __restrict__ X, int64_t ldx,
+                            double* __restrict__ Y, int64_t ldy, int64_t n, int64_t k) {
+  for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
+    const double* x = X + j * ldx * W;
+    double* y = Y + j * ldy * W;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * W;
+         i += (int64_t)gridDim.x * blockDim.x)
+      y[i] += a * x[i];
+  }
+}
+
+// A = (A + A^H)/2, each unordered pair handled once (i <= j)
+template <bool CPLX>
+__global__ void herm_part_k(double* __restrict__ A, int64_t lda, int64_t n) {
+  const int W = CPLX ? 2 : 1;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i <= j;
+         i += (int64_t)gridDim.x * blockDim.x) {
+      double* a = A + (i + j * lda) * W;
+      double* b = A + (j + i * lda) * W;
+      if (CPLX) {
+        const double re = 0.5 * (a[0] + b[0]);
+        const double im = 0.5 * (a[1] - b[1]);
+        a[0] = re;
+        a[1] = im;
+        b[0] = re;
+        b[1] = -im;
+      } else {
+        const double v = 0.5 * (a[0] + b[0]);
+        a[0] = v;
+        b[0] = v;
+      }
+    }
+  }
+}
+
+__global__ void to_f32_k(const double* __restrict__ src, int64_t lds, float* __restrict__ dst,
+                         int64_t rows_scalars, int64_t n, int W) {
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) {
+    const double* s = src + j * lds * W;
+    float* d = dst + j * rows_scalars;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows_scalars;
+         i += (int64_t)gridDim.x * blockDim.x)
+      d[i] = (float)s[i];
+  }
+}
+
+__global__ void check_finite_k(const double* __restrict__ X, int64_t ldx, int64_t rows_scalars,
+                               int64_t k, int W, int* flags) {
+  for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
+    const double* c = X + j * ldx * W;
+    bool bad = false;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < rows_scalars;
+         i += (int64_t)gridDim.x * blockDim.x)
+      bad |= !isfinite(c[i]);
+    if (bad) flags[0] = 1;
+  }
+}
+
+// ------------------------------------------------------------------ Lanczos
+// Block matrix-vector product W = H Q for nv <= 8 vectors, H read once from
+// HBM (column-major, coalesced along rows).  The columns of H are split over
+// gridDim.y slices; each slice writes its partial sums, which the reduction
+// kernel adds in a fixed order (deterministic).
+constexpr int LZ_ROWS_PER_THREAD = 2;
+constexpr int LZ_ROWS = TPB * LZ_ROWS_PER_THREAD;
+constexpr int LZ_COLS_STAGE = 64;
+
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, int64_t ldh,
+                                                 int64_t n, const double* __restrict__ Q, int nv,
+                                                 double* __restrict__ part, int64_t cols_per) {
+  const int W = CPLX ? 2 : 1;
+  __shared__ double qs[LZ_COLS_STAGE][8][2];
+  const int64_t r0 = (int64_t)blockIdx.x * LZ_ROWS;
+  const int64_t c0 = (int64_t)blockIdx.y * cols_per;
+  const int64_t c1 = c0 + cols_per < n ? c0 + cols_per : n;
+  double accr[LZ_ROWS_PER_THREAD][8], acci[LZ_ROWS_PER_THREAD][8];
+#pragma unroll
+  for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r)
+#pragma unroll
+    for (int v = 0; v < 8; ++v) accr[r][v] = acci[r][v] = 0.0;
+
+  for (int64_t cs = c0; cs < c1; cs += LZ_COLS_STAGE) {
+    const int ncs = (int)(c1 - cs < LZ_COLS_STAGE ? c1 - cs : LZ_COLS_STAGE);
+    __syncthreads();
+    for (int e = threadIdx.x; e < ncs * nv; e += TPB) {
+      const int c = e % ncs, v = e / ncs;
+      const double* q = Q + ((cs + c) + (int64_t)v * n) * W;
+      qs[c][v][0] = q[0];
+      qs[c][v][1] = CPLX ? q[1] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < ncs; ++c) {
+      const double* hc = H + (cs + c) * ldh * W;
+#pragma unroll
+      for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
+        const int64_t i = r0 + threadIdx.x + r * TPB;
+        if (i < n) {
+          double hr, hi = 0.0;
+          if (CPLX) {
+            const d2v h = *reinterpret_cast<const d2v*>(hc + 2 * i);
+            hr = h.x;
+            hi = h.y;
+          } else {
+            hr = hc[i];
+          }
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            if (v < nv) {
+              const double qr = qs[c][v][0], qi = qs[c][v][1];
+              accr[r][v] += hr * qr - hi * qi;
+              if (CPLX) acci[r][v] += hr * qi + hi * qr;
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
+    const int64_t i = r0 + threadIdx.x + r * TPB;
+    if (i < n) {
+      for (int v = 0; v < nv; ++v) {
+        double* p = part + (((int64_t)blockIdx.y * nv + v) * n + i) * W;
+        p[0] = accr[r][v];
+        if (CPLX) p[1] = acci[r][v];
+      }
+    }
+  }
+}
+
+// block-wide sum of nv values per thread into out[blockIdx.x*nv + v]
+__device__ inline void block_sum_store(double* vals, int nv, double* out) {
+  __shared__ double red[TPB / 64][8];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int v = 0; v < nv; ++v) {
+    double x = vals[v];
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    if (lane == 0) red[wave][v] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < nv) {
+    double s = 0;
+    for (int w = 0; w < TPB / 64; ++w) s += red[w][threadIdx.x];
+    out[(int64_t)blockIdx.x * nv + threadIdx.x] = s;
+  }
+}
+
+// W = sum of gemv partials - beta_prev * Q_prev ; dotp = Re(Q_cur^H W) partials
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void lz_reduce_k(const double* __restrict__ part, int splits,
+                                                   int64_t n, int nv,
+                                                   const double* __restrict__ qprev,
+                                                   const double* __restrict__ qcur,
+                                                   const double* __restrict__ beta_prev,
+                                                   double* __restrict__ w, double* dotp) {
+  const int W = CPLX ? 2 : 1;
+  double dots[8];
+  for (int v = 0; v < 8; ++v) dots[v] = 0.0;
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    for (int v = 0; v < nv; ++v) {
+      double sr = 0, si = 0;
+      for (int z = 0; z < splits; ++z) {
+        const double* p = part + (((int64_t)z * nv + v) * n + i) * W;
+        sr += p[0];
+        if (CPLX) si += p[1];
+      }
+      const int64_t o = (i + (int64_t)v * n) * W;
+      const double bp = beta_prev ? beta_prev[v] : 0.0;
+      sr -= bp * qprev[o];
+      if (CPLX) si -= bp * qprev[o + 1];
+      w[o] = sr;
+      if (CPLX) w[o + 1] = si;
+      dots[v] += qcur[o] * sr + (CPLX ? qcur[o + 1] * si : 0.0);
+    }
+  }
+  block_sum_store(dots, nv, dotp);
+}
+
+// alpha = sum(dotp); W -= alpha * Q_cur (skipped when with_alpha == 0);
+// nrmp = partial ||W||^2
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void lz_orth_k(const double* __restrict__ dotp, int nblk,
+                                                 int64_t n, int nv, int with_alpha,
+                                                 const double* __restrict__ qcur,
+                                                 double* __restrict__ w, double* alpha_out,
+                                                 double* nrmp) {
+  const int W = CPLX ? 2 : 1;
+  double alpha[8], nrm[8];
+  for (int v = 0; v < 8; ++v) {
+    alpha[v] = 0.0;
+    nrm[v] = 0.0;
+  }
+  if (with_alpha) {
+    for (int v = 0; v < nv; ++v) {
+      double s = 0;
+      for (int b = 0; b < nblk; ++b) s += dotp[(int64_t)b * nv + v];
+      alpha[v] = s;
+    }
+    if (blockIdx.x == 0 && threadIdx.x < nv) alpha_out[threadIdx.x] = alpha[threadIdx.x];
+  }
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    for (int v = 0; v < nv; ++v) {
+      const int64_t o = (i + (int64_t)v * n) * W;
+      double xr = w[o], xi = CPLX ? w[o + 1] : 0.0;
+      if (with_alpha) {
+        xr -= alpha[v] * qcur[o];
+        if (CPLX) xi -= alpha[v] * qcur[o + 1];
+        w[o] = xr;
+        if (CPLX) w[o + 1] = xi;
+      }
+      nrm[v] += xr * xr + xi * xi;
+    }
+  }
+  block_sum_store(nrm, nv, nrmp);
+}
+
+// beta = sqrt(sum(nrmp)); Q_next = W / beta (0 if beta == 0)
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void lz_normalize_k(const double* __restrict__ nrmp, int nblk,
+                                                      int64_t n, int nv,
+                                                      const double* __restrict__ w,
+                                                      double* __restrict__ qnext,
+                                                      double* beta_out) {
+  const int W = CPLX ? 2 : 1;
+  double inv[8];
+  for (int v = 0; v < nv; ++v) {
+    double s = 0;
+    for (int b = 0; b < nblk; ++b) s += nrmp[(int64_t)b * nv + v];
+    const double beta = sqrt(s);
+    inv[v] = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && beta_out) beta_out[v] = beta;
+  }
+  for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
+    for (int v = 0; v < nv; ++v) {
+      const int64_t o = (i + (int64_t)v * n) * W;
+      qnext[o] = w[o] * inv[v];
+      if (CPLX) qnext[o + 1] = w[o + 1] * inv[v];
+    }
+  }
+}
+
+constexpr int LZ_VEC_BLOCKS = 128;
+
+int lz_splits(int64_t n) {
+  const int64_t row_blocks = (n + LZ_ROWS - 1) / LZ_ROWS;
+  int64_t s = (2048 + row_blocks - 1) / row_blocks;
+  const int64_t smax = (n + 63) / 64;
+  if (s > smax) s = smax;
+  if (s > 64) s = 64;
+  if (s < 1) s = 1;
+  return (int)s;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ host launchers
+void fill_zero(void* p, int64_t bytes, hipStream_t st) {
+  if (bytes <= 0) return;
+  if (bytes % 4 == 0 && (reinterpret_cast<uintptr_t>(p) & 3) == 0)
+    hipLaunchKernelGGL(fill_zero_k, dim3(blocks_for(bytes / 4, TPB * 4, 4096)), dim3(TPB), 0, st,
+                       static_cast<uint32_t*>(p), bytes / 4);
+  else
+    hipLaunchKernelGGL(fill_zero_bytes_k, dim3(blocks_for(bytes, TPB * 4, 4096)), dim3(TPB), 0,
+                       st, static_cast<unsigned char*>(p), bytes);
+  CHASE_HIP(hipGetLastError());
+}
+
+static void copy_impl(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
+                      int64_t k, const int* perm, hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  const int64_t rows = n * (cplx ? 2 : 1);
+  dim3 grid(blocks_for(rows, TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
+  if (cplx)
+    hipLaunchKernelGGL(copy_cols_k<2>, grid, dim3(TPB), 0, st, static_cast<const double*>(src),
+                       lds, static_cast<double*>(dst), ldd, n, k, perm);
+  else
+    hipLaunchKernelGGL(copy_cols_k<1>, grid, dim3(TPB), 0, st, static_cast<const double*>(src),
+                       lds, static_cast<double*>(dst), ldd, n, k, perm);
+  CHASE_HIP(hipGetLastError());
+}
+
+void copy_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
+               int64_t k, hipStream_t st) {
+  copy_impl(cplx, src, lds, dst, ldd, n, k, nullptr, st);
+}
+
+void gather_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
+                 int64_t k, const int* perm_dev, hipStream_t st) {
+  copy_impl(cplx, src, lds, dst, ldd, n, k, perm_dev, st);
+}
+
+void splitk_reduce(bool cplx, const void* ws, int splits, int64_t M, int64_t N, void* C,
+                   int64_t ldc, bool herm, hipStream_t st) {
+  const int nb = blocks_for(M * N, TPB, 8192);
+  if (cplx)
+    hipLaunchKernelGGL(splitk_reduce_k<true>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<const double*>(ws), splits, M, N, static_cast<double*>(C),
+                       ldc, herm);
+  else
+    hipLaunchKernelGGL(splitk_reduce_k<false>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<const double*>(ws), splits, M, N, static_cast<double*>(C),
+                       ldc, herm);
+  CHASE_HIP(hipGetLastError());
+}
+
+void gram_scale(bool cplx, void* S, int64_t lds, int64_t k, double shift, double* d, int* flags,
+                hipStream_t st) {
+  const int nb1 = blocks_for(k, TPB, 1024);
+  const int nb2 = blocks_for(k * k, TPB, 8192);
+  if (cplx) {
+    hipLaunchKernelGGL(gram_diag_k<true>, dim3(nb1), dim3(TPB), 0, st,
+                       static_cast<const double*>(S), lds, k, d, flags);
+    hipLaunchKernelGGL(gram_apply_k<true>, dim3(nb2), dim3(TPB), 0, st, static_cast<double*>(S),
+                       lds, k, d, shift);
+  } else {
+    hipLaunchKernelGGL(gram_diag_k<false>, dim3(nb1), dim3(TPB), 0, st,
+                       static_cast<const double*>(S), lds, k, d, flags);
+    hipLaunchKernelGGL(gram_apply_k<false>, dim3(nb2), dim3(TPB), 0, st, static_cast<double*>(S),
+                       lds, k, d, shift);
+  }
+  CHASE_HIP(hipGetLastError());
+}
+
+void triu_rowscale(bool cplx, void* R, int64_t ldr, int64_t k, const double* d, hipStream_t st) {
+  const int nb = blocks_for(k * k, TPB, 8192);
+  if (cplx)
+    hipLaunchKernelGGL(triu_rowscale_k<true>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<double*>(R), ldr, k, d);
+  else
+    hipLaunchKernelGGL(triu_rowscale_k<false>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<double*>(R), ldr, k, d);
+  CHASE_HIP(hipGetLastError());
+}
+
+void diag_real(bool cplx, const void* A, int64_t lda, int64_t k, double* out, hipStream_t st) {
+  const int nb = blocks_for(k, TPB, 1024);
+  if (cplx)
+    hipLaunchKernelGGL(diag_real_k<true>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<const double*>(A), lda, k, out);
+  else
+    hipLaunchKernelGGL(diag_real_k<false>, dim3(nb), dim3(TPB), 0, st,
+                       static_cast<const double*>(A), lda, k, out);
+  CHASE_HIP(hipGetLastError());
+}
+
+void resid_finish(const double* partial, int tiles, int64_t N, double inv_scale, double* res,
+                  hipStream_t st) {
+  hipLaunchKernelGGL(resid_finish_k, dim3(blocks_for(N, TPB, 1024)), dim3(TPB), 0, st, partial,
+                     tiles, N, inv_scale, res);
+  CHASE_HIP(hipGetLastError());
+}
+
+void scale_cols(bool cplx, void* V, int64_t ldv, int64_t n, int64_t k, const double* g,
+                hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  dim3 grid(blocks_for(n * (cplx ? 2 : 1), TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
+  if (cplx)
+    hipLaunchKernelGGL(scale_cols_k<true>, grid, dim3(TPB), 0, st, static_cast<double*>(V), ldv,
+                       n, k, g);
+  else
+    hipLaunchKernelGGL(scale_cols_k<false>, grid, dim3(TPB), 0, st, static_cast<double*>(V), ldv,
+                       n, k, g);
+  CHASE_HIP(hipGetLastError());
+}
+
+void axpy_cols(bool cplx, double a, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t n,
+               int64_t k, hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  dim3 grid(blocks_for(n * (cplx ? 2 : 1), TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
+  if (cplx)
+    hipLaunchKernelGGL(axpy_cols_k<2>, grid, dim3(TPB), 0, st, a, static_cast<const double*>(X),
+                       ldx, static_cast<double*>(Y), ldy, n, k);
+  else
+    hipLaunchKernelGGL(axpy_cols_k<1>, grid, dim3(TPB), 0, st, a, static_cast<const double*>(X),
+                       ldx, static_cast<double*>(Y), ldy, n, k);
+  CHASE_HIP(hipGetLastError());
+}
+
+void herm_part(bool cplx, void* A, int64_t lda, int64_t n, hipStream_t st) {
+  if (n <= 0) return;
+  dim3 grid(blocks_for(n, TPB, 64), (unsigned)(n < 65535 ? n : 65535));
+  if (cplx)
+    hipLaunchKernelGGL(herm_part_k<true>, grid, dim3(TPB), 0, st, static_cast<double*>(A), lda, n);
+  else
+    hipLaunchKernelGGL(herm_part_k<false>, grid, dim3(TPB), 0, st, static_cast<double*>(A), lda,
+                       n);
+  CHASE_HIP(hipGetLastError());
+}
+
+void to_f32(bool cplx, const void* src, int64_t lds, void* dst, int64_t n, hipStream_t st) {
+  const int W = cplx ? 2 : 1;
+  dim3 grid(blocks_for(n * W, TPB * 4, 64), (unsigned)(n < 65535 ? n : 65535));
+  hipLaunchKernelGGL(to_f32_k, grid, dim3(TPB), 0, st, static_cast<const double*>(src), lds,
+                     static_cast<float*>(dst), n * W, n, W);
+  CHASE_HIP(hipGetLastError());
+}
+
+void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, int* flags,
+                  hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  const int W = cplx ? 2 : 1;
+  dim3 grid(blocks_for(n * W, TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
+  hipLaunchKernelGGL(check_finite_k, grid, dim3(TPB), 0, st, static_cast<const double*>(X), ldx,
+                     n * W, k, W, flags);
+  CHASE_HIP(hipGetLastError());
+}
+
+size_t lanczos_bytes(bool cplx, int64_t n, int nv, int steps, int* max_splits) {
+  const int W = cplx ? 2 : 1;
+  const int s = lz_splits(n);
+  if (max_splits) *max_splits = s;
+  size_t b = 0;
+  b += 3 * (size_t)n * nv * W * 8;            // q_prev, q_cur, w
+  b += (size_t)s * nv * n * W * 8;            // gemv partials
+  b += 2 * (size_t)LZ_VEC_BLOCKS * nv * 8;    // dot / norm partials
+  b += 2 * (size_t)steps * nv * 8;            // alpha, beta
+  return b;
+}
+
+void lanczos_run(bool cplx, const void* Hv, int64_t ldh, int64_t n, const void* Sv, int nv,
+                 int steps, LanczosBufs& b, hipStream_t st) {
+  const int W = cplx ? 2 : 1;
+  const double* H = static_cast<const double*>(Hv);
+  double* qprev = static_cast<double*>(b.q_prev);
+  double* qcur = static_cast<double*>(b.q_cur);
+  double* w = static_cast<double*>(b.w);
+  double* part = static_cast<double*>(b.wpart);
+  const int splits = b.max_splits;
+  const int64_t cols_per = (n + splits - 1) / splits;
+  const int row_blocks = (int)((n + LZ_ROWS - 1) / LZ_ROWS);
+  const int vb = (int)std::min<int64_t>(LZ_VEC_BLOCKS, (n + TPB - 1) / TPB);
+
+  // q_1 = s / ||s|| ; q_0 = 0
+  CHASE_HIP(hipMemcpyAsync(w, Sv, (size_t)n * nv * W * 8, hipMemcpyDeviceToDevice, st));
+  fill_zero(qprev, (int64_t)n * nv * W * 8, st);
+  auto orth = [&](int with_alpha, double* alpha_out) {
+    if (cplx)
+      hipLaunchKernelGGL(lz_orth_k<true>, dim3(vb), dim3(TPB), 0, st, b.dotp, vb, n, nv,
+                         with_alpha, qcur, w, alpha_out, b.nrmp);
+    else
+      hipLaunchKernelGGL(lz_orth_k<false>, dim3(vb), dim3(TPB), 0, st, b.dotp, vb, n, nv,
+                         with_alpha, qcur, w, alpha_out, b.nrmp);
+  };
+  auto normalize = [&](double* dst, double* beta_out) {
+    if (cplx)
+      hipLaunchKernelGGL(lz_normalize_k<true>, dim3(vb), dim3(TPB), 0, st, b.nrmp, vb, n, nv, w,
+                         dst, beta_out);
+    else
+      hipLaunchKernelGGL(lz_normalize_k<false>, dim3(vb), dim3(TPB), 0, st, b.nrmp, vb, n, nv, w,
+                         dst, beta_out);
+  };
+  orth(0, nullptr);
+  normalize(qcur, nullptr);
+  for (int j = 0; j < steps; ++j) {
+    if (cplx)
+      hipLaunchKernelGGL(lz_gemv_k<true>, dim3(row_blocks, splits), dim3(TPB), 0, st, H, ldh, n,
+                         qcur, nv, part, cols_per);
+    else
+      hipLaunchKernelGGL(lz_gemv_k<false>, dim3(row_blocks, splits), dim3(TPB), 0, st, H, ldh, n,
+                         qcur, nv, part, cols_per);
+    const double* bprev = j > 0 ? b.beta + (int64_t)(j - 1) * nv : nullptr;
+    if (cplx)
+      hipLaunchKernelGGL(lz_reduce_k<true>, dim3(vb), dim3(TPB), 0, st, part, splits, n, nv,
+                         qprev, qcur, bprev, w, b.dotp);
+    else
+      hipLaunchKernelGGL(lz_reduce_k<false>, dim3(vb), dim3(TPB), 0, st, part, splits, n, nv,
+                         qprev, qcur, bprev, w, b.dotp);
+    orth(1, b.alpha + (int64_t)j * nv);
+    // q_{j+1} overwrites q_{j-1}
+    normalize(qprev, b.beta + (int64_t)j * nv);
+    std::swap(qprev, qcur);
+    CHASE_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace chase

@@ -1,0 +1,900 @@
+// ChASE driver (Algorithm 1) on one MI355X and the C ABI of include/chase.h.
+//
+// H stays resident and const in HBM for the whole solve; the search block
+// V (n x (nev+nex)) and two scratch blocks of the same shape live in the
+// handle's workspace, allocated once (the paper pre-allocates its library
+// buffers before the main loop).  Per iteration the host only sees a few KB:
+// the QR pivots, the Ritz values and the residual norms.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "hostmath.h"
+
+using namespace chase;
+
+struct chase_handle_s {
+  chase_dtype dtype;
+  bool cplx;
+  int64_t n;
+  int nev, nex, ne;
+  chase_opts opts;
+  size_t esz;  // bytes per element (16 or 8)
+  int device;
+  // n x ne blocks, ld n
+  void *V = nullptr, *W = nullptr, *Z = nullptr;
+  // ne x ne matrices
+  void *G = nullptr, *R = nullptr;
+  void* ws = nullptr;  // split-K workspace
+  size_t ws_elems = 0;
+  double *d_scale = nullptr, *d_evals = nullptr, *d_res = nullptr, *d_partial = nullptr,
+         *d_E = nullptr, *d_g = nullptr;
+  int *d_flags = nullptr, *d_info = nullptr, *d_perm = nullptr;
+  void* tau = nullptr;
+  LanczosBufs lz{};
+  void* H32 = nullptr;  // low-precision copy of H for the FP32 filter
+  // filter tape (record_tape)
+  void* tape = nullptr;
+  size_t tape_bytes = 0;
+  std::vector<int> tape_deg;
+  std::vector<Coef> tape_coef;
+  int tape_k = 0;
+  bool tape_valid = false;
+  rocblas_handle rb = nullptr;
+  std::vector<hipEvent_t> evs;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+char* off(void* p, int64_t elems, size_t esz) { return static_cast<char*>(p) + elems * (int64_t)esz; }
+
+void* dev_alloc(chase_handle_s* h, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error(CHASE_ERR_NOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  h->allocs.push_back(p);
+  return p;
+}
+
+void rb_check(rocblas_status s, const char* what) {
+  if (s != rocblas_status_success)
+    throw Error(CHASE_ERR_HIP, std::string(what) + " failed: " + rocblas_status_to_string(s));
+}
+
+size_t splitk_ws_elems(int ne) {
+  size_t mx = 0;
+  for (int k = 1; k <= ne; ++k) {
+    int s;
+    int64_t ks;
+    // K is at least ne (the library's projections have K = n >= ne)
+    splitk_plan(k, k, INT64_MAX / 4, &s, &ks);
+    mx = std::max(mx, (size_t)s * k * k);
+  }
+  return mx;
+}
+
+struct Sizes {
+  size_t blocks, small, lz, ws, h32, total;
+  int lz_splits;
+};
+
+Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
+  Sizes s{};
+  const bool cplx = dt == CHASE_C128;
+  const size_t esz = cplx ? 16 : 8;
+  const int64_t ne = nev + nex;
+  s.blocks = 3 * (size_t)n * ne * esz + 2 * (size_t)ne * ne * esz;
+  s.ws = splitk_ws_elems((int)ne) * esz;
+  s.small = (size_t)ne * 8 * 5 + (size_t)gemm_row_tiles(n) * ne * 8 + 64 + (size_t)ne * 4 +
+            (size_t)ne * esz;
+  s.lz = lanczos_bytes(cplx, n, o.lanczos_vecs, o.lanczos_steps, &s.lz_splits);
+  s.h32 = o.filter_prec == CHASE_PREC_FP32 ? (size_t)n * n * esz / 2 : 0;
+  s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
+  return s;
+}
+
+void validate_opts(const chase_opts& o) {
+  CHASE_REQUIRE(o.max_deg >= 2 && o.max_deg <= 1000, "max_deg out of range [2,1000]");
+  CHASE_REQUIRE(o.deg_extra >= 0, "deg_extra < 0");
+  CHASE_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 200, "lanczos_steps out of range");
+  CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
+  CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
+  CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32,
+                "unknown filter_prec");
+}
+
+// ------------------------------------------------------------------ GEMM helpers
+GemmArgs gargs(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, const void* B,
+               int64_t ldb, void* C, int64_t ldc) {
+  GemmArgs g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  g.alpha = 1.0;
+  return g;
+}
+
+// C (k1 x k2, ld ldc) = A^H B for tall A (K x k1), B (K x k2); herm: (S+S^H)/2
+void gram(chase_handle_s* h, const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K,
+          int64_t k1, int64_t k2, void* C, int64_t ldc, bool herm, hipStream_t st) {
+  int splits;
+  int64_t ks;
+  splitk_plan(k1, k2, K, &splits, &ks);
+  CHASE_REQUIRE((size_t)splits * k1 * k2 <= h->ws_elems, "split-K workspace too small");
+  GemmArgs g = gargs(k1, k2, K, A, lda, B, ldb, h->ws, k1);
+  g.splits = splits;
+  g.kslice = ks;
+  gemm(h->cplx, PREC_F64, OP_C, OP_N, EPI_SPLITK, g, st);
+  splitk_reduce(h->cplx, h->ws, splits, k1, k2, C, ldc, herm, st);
+}
+
+void gemm_nn(chase_handle_s* h, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
+             const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+  GemmArgs g = gargs(M, N, K, A, lda, B, ldb, C, ldc);
+  gemm(h->cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
+}
+
+// ------------------------------------------------------------------ filter
+struct FilterTiming {
+  int64_t matvecs = 0;
+  double ktime = 0.0;  // seconds of filter GEMMs (HIP events)
+  int64_t launches = 0;
+};
+
+// X (n x k, ld ldx) <- p_{m_a}(H) x_a ; Wb (n x k, ld ldw) ping-pong scratch.
+// degrees non-decreasing, even, >= 2.
+void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t ldx, void* Wb,
+                int64_t ldw, int k, const int* deg, double b_sup, double mu_1, double mu_ne,
+                Prec prec, bool tape, FilterTiming& ft, hipStream_t st) {
+  if (k <= 0) return;
+  const int64_t n = h->n;
+  const int mmax = deg[k - 1];
+  const std::vector<Coef> cf = cheb_coefficients(mmax, b_sup, mu_1, mu_ne);
+  const void* Ah = H;
+  int64_t lda = ldh;
+  int a_f32 = 0;
+  if (prec == PREC_F32 && h->H32) {
+    Ah = h->H32;
+    lda = n;
+    a_f32 = 1;
+  }
+  if (tape) {
+    // slot s holds X_s of all k columns (columns not active at step s keep
+    // their last value, which the adjoint never reads)
+    copy_cols(h->cplx, X, ldx, h->tape, n, n, k, st);
+  }
+  const size_t need_ev = 2 * (size_t)mmax;
+  while (h->evs.size() < need_ev) {
+    hipEvent_t e;
+    CHASE_HIP(hipEventCreate(&e));
+    h->evs.push_back(e);
+  }
+  for (int s = 1; s <= mmax; ++s) {
+    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    const int cols = k - a0;
+    if (cols <= 0) continue;
+    void* src = (s & 1) ? X : Wb;  // X_{s-1}
+    void* dst = (s & 1) ? Wb : X;  // X_s over X_{s-2}
+    const int64_t lds = (s & 1) ? ldx : ldw, ldd = (s & 1) ? ldw : ldx;
+    GemmArgs g = gargs(n, cols, n, Ah, lda, off(src, a0 * lds, h->esz), lds,
+                       off(dst, a0 * ldd, h->esz), ldd);
+    g.alpha = cf[s - 1].alpha;
+    g.gamma = cf[s - 1].gamma;
+    g.beta = cf[s - 1].beta;
+    g.a_f32 = a_f32;
+    CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
+    gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
+    CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
+    ft.matvecs += cols;
+    ft.launches += 1;
+    if (tape)
+      copy_cols(h->cplx, off(dst, a0 * ldd, h->esz), ldd,
+                off(h->tape, ((int64_t)s * k + a0) * n, h->esz), n, n, cols, st);
+  }
+  CHASE_HIP(hipStreamSynchronize(st));
+  for (int s = 1; s <= mmax; ++s) {
+    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    if (k - a0 <= 0) continue;
+    float ms = 0.f;
+    CHASE_HIP(hipEventElapsedTime(&ms, h->evs[2 * (s - 1)], h->evs[2 * (s - 1) + 1]));
+    ft.ktime += ms * 1e-3;
+  }
+  if (tape) {
+    h->tape_deg.assign(deg, deg + k);
+    h->tape_coef = cf;
+    h->tape_k = k;
+    h->tape_valid = true;
+  }
+}
+
+void ensure_tape(chase_handle_s* h, int k, int mmax) {
+  const size_t need = (size_t)(mmax + 1) * h->n * k * h->esz;
+  if (h->tape && h->tape_bytes >= need) return;
+  if (h->tape) {
+    CHASE_HIP(hipFree(h->tape));
+    h->tape = nullptr;
+    h->tape_bytes = 0;
+  }
+  size_t fr = 0, tot = 0;
+  CHASE_HIP(hipMemGetInfo(&fr, &tot));
+  if (need > fr) throw Error(CHASE_ERR_NOMEM, "filter tape does not fit in device memory");
+  if (hipMalloc(&h->tape, need) != hipSuccess) {
+    (void)hipGetLastError();
+    h->tape = nullptr;
+    throw Error(CHASE_ERR_NOMEM, "filter tape allocation failed");
+  }
+  h->tape_bytes = need;
+}
+
+// ------------------------------------------------------------------ QR
+// Orthonormalise X (n x k, ld ldx) keeping its first L columns.  Cholesky QR
+// with column scaling, twice (CholeskyQR2); when the first factor reveals a
+// condition number near 1/sqrt(eps), the first pass is redone with a shift
+// and followed by two plain passes (shifted CholeskyQR3); if even that
+// breaks down, Householder QR.  Scratch: Wb (n x k, ld n), R (k x k).
+void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, chase_stats* stats,
+             hipStream_t st) {
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  void* R = h->R;
+  const int64_t ldr = k;
+  bool shifted = false;
+  int total = 2;
+  std::vector<double> diag(k);
+  int hinfo[2];
+  for (int pass = 0; pass < total; ++pass) {
+    gram(h, X, ldx, X, ldx, n, k, k, R, ldr, true, st);
+    double shift = 0.0;
+    if (shifted && pass == 0) {
+      const double u = 1.1102230246251565e-16;
+      shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * u * (double)k;
+    }
+    fill_zero(h->d_flags, 2 * sizeof(int), st);
+    gram_scale(cplx, R, ldr, k, shift, h->d_scale, h->d_flags, st);
+    if (cplx)
+      rb_check(rocsolver_zpotrf(h->rb, rocblas_fill_upper, k,
+                                static_cast<rocblas_double_complex*>(R), ldr, h->d_info),
+               "zpotrf");
+    else
+      rb_check(rocsolver_dpotrf(h->rb, rocblas_fill_upper, k, static_cast<double*>(R), ldr,
+                                h->d_info),
+               "dpotrf");
+    CHASE_HIP(hipMemcpyAsync(&hinfo[0], h->d_info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipMemcpyAsync(&hinfo[1], h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    if (pass == 0) {
+      diag_real(cplx, R, ldr, k, h->d_res, st);
+      CHASE_HIP(hipMemcpyAsync(diag.data(), h->d_res, k * sizeof(double), hipMemcpyDeviceToHost,
+                               st));
+    }
+    CHASE_HIP(hipStreamSynchronize(st));
+    bool ok = hinfo[0] == 0 && hinfo[1] == 0;
+    if (ok && pass == 0) {
+      double dmin = INFINITY;
+      for (double d : diag) dmin = std::min(dmin, std::fabs(d));
+      if (!(dmin >= 1e-6) && !shifted) ok = false;
+    }
+    if (!ok) {
+      if (pass == 0 && !shifted && hinfo[1] == 0) {
+        shifted = true;
+        total = 3;
+        pass = -1;
+        if (stats) stats->qr_shifted++;
+        continue;
+      }
+      // Householder fallback (locked columns restored afterwards)
+      if (stats) stats->qr_householder++;
+      if (L > 0) copy_cols(cplx, X, ldx, Wb, n, n, L, st);
+      if (cplx) {
+        rb_check(rocsolver_zgeqrf(h->rb, n, k, static_cast<rocblas_double_complex*>(X), ldx,
+                                  static_cast<rocblas_double_complex*>(h->tau)),
+                 "zgeqrf");
+        rb_check(rocsolver_zungqr(h->rb, n, k, k, static_cast<rocblas_double_complex*>(X), ldx,
+                                  static_cast<rocblas_double_complex*>(h->tau)),
+                 "zungqr");
+      } else {
+        rb_check(rocsolver_dgeqrf(h->rb, n, k, static_cast<double*>(X), ldx,
+                                  static_cast<double*>(h->tau)),
+                 "dgeqrf");
+        rb_check(rocsolver_dorgqr(h->rb, n, k, k, static_cast<double*>(X), ldx,
+                                  static_cast<double*>(h->tau)),
+                 "dorgqr");
+      }
+      if (L > 0) copy_cols(cplx, Wb, n, X, ldx, n, L, st);
+      fill_zero(h->d_flags, sizeof(int), st);
+      check_finite(cplx, X, ldx, n, k, h->d_flags, st);
+      CHASE_HIP(hipMemcpyAsync(&hinfo[1], h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+      CHASE_HIP(hipStreamSynchronize(st));
+      if (hinfo[1]) throw Error(CHASE_ERR_NUMERIC, "QR breakdown (non-finite values)");
+      return;
+    }
+    if (cplx)
+      rb_check(rocsolver_ztrtri(h->rb, rocblas_fill_upper, rocblas_diagonal_non_unit, k,
+                                static_cast<rocblas_double_complex*>(R), ldr, h->d_info),
+               "ztrtri");
+    else
+      rb_check(rocsolver_dtrtri(h->rb, rocblas_fill_upper, rocblas_diagonal_non_unit, k,
+                                static_cast<double*>(R), ldr, h->d_info),
+               "dtrtri");
+    triu_rowscale(cplx, R, ldr, k, h->d_scale, st);
+    // Wb = X * (D R^{-1}); the locked columns keep their values
+    gemm_nn(h, n, k - L, k, X, ldx, off(R, (int64_t)L * ldr, h->esz), ldr, Wb, n, st);
+    copy_cols(cplx, Wb, n, off(X, (int64_t)L * ldx, h->esz), ldx, n, k - L, st);
+  }
+}
+
+// ------------------------------------------------------------------ Rayleigh-Ritz + residual
+// Q (n x k, ld ldq) orthonormal -> Ritz vectors; ritz/res on the device
+// (h->d_evals, h->d_res).  Scratch: P (n x k, ld n), Zb (n x k, ld n).
+void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq, int k,
+             double norm_scale, void* P, void* Zb, double* t_rr, double* t_resid,
+             hipStream_t st) {
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  auto t0 = clk::now();
+  // P = H Q   (the HEMM of the Rayleigh-Ritz step)
+  gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
+  // G = Q^H P, exactly Hermitian
+  gram(h, Q, ldq, P, n, n, k, k, h->G, k, true, st);
+  if (cplx)
+    rb_check(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
+                              static_cast<rocblas_double_complex*>(h->G), k, h->d_evals, h->d_E,
+                              h->d_info),
+             "zheevd");
+  else
+    rb_check(rocsolver_dsyevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
+                              static_cast<double*>(h->G), k, h->d_evals, h->d_E, h->d_info),
+             "dsyevd");
+  // Ritz vectors Z = Q W
+  gemm_nn(h, n, k, k, Q, ldq, h->G, k, Zb, n, st);
+  CHASE_HIP(hipStreamSynchronize(st));
+  auto t1 = clk::now();
+  // residual: (P W) - Z diag(theta), column norms, without a second HEMM
+  GemmArgs g = gargs(n, k, k, P, n, h->G, k, nullptr, 0);
+  g.lambda = h->d_evals;
+  g.V = Zb;
+  g.ldv = n;
+  g.partial = h->d_partial;
+  gemm(cplx, PREC_F64, OP_N, OP_N, EPI_RESID, g, st);
+  resid_finish(h->d_partial, gemm_row_tiles(n), k, 1.0 / norm_scale, h->d_res, st);
+  copy_cols(cplx, Zb, n, Q, ldq, n, k, st);
+  CHASE_HIP(hipStreamSynchronize(st));
+  auto t2 = clk::now();
+  if (t_rr) *t_rr += secs(t0, t1);
+  if (t_resid) *t_resid += secs(t1, t2);
+}
+
+void check_info(chase_handle_s* h, hipStream_t st, const char* what) {
+  int info = 0;
+  CHASE_HIP(hipMemcpyAsync(&info, h->d_info, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipStreamSynchronize(st));
+  if (info != 0)
+    throw Error(CHASE_ERR_NUMERIC, std::string(what) + " did not converge (info=" +
+                                       std::to_string(info) + ")");
+}
+
+Bounds do_lanczos(chase_handle_s* h, const void* H, int64_t ldh, const void* S, int nv, int steps,
+                  std::vector<double>* a_out, std::vector<double>* b_out, std::vector<int>* lens,
+                  hipStream_t st) {
+  lanczos_run(h->cplx, H, ldh, h->n, S, nv, steps, h->lz, st);
+  std::vector<double> a((size_t)steps * nv), b((size_t)steps * nv);
+  CHASE_HIP(hipMemcpyAsync(a.data(), h->lz.alpha, a.size() * 8, hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipMemcpyAsync(b.data(), h->lz.beta, b.size() * 8, hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipStreamSynchronize(st));
+  for (double x : a)
+    if (!std::isfinite(x)) throw Error(CHASE_ERR_NUMERIC, "non-finite Lanczos coefficients");
+  Bounds bd = lanczos_bounds(a, b, nv, steps, h->n, h->ne, lens);
+  if (a_out) *a_out = a;
+  if (b_out) *b_out = b;
+  return bd;
+}
+
+template <typename F>
+chase_status guarded(F&& f) {
+  try {
+    f();
+    g_last_error.clear();
+    return CHASE_OK;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.status;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return CHASE_ERR_HIP;
+  }
+}
+
+void set_stream(chase_handle_s* h, hipStream_t st) {
+  CHASE_HIP(hipSetDevice(h->device));
+  rb_check(rocblas_set_stream(h->rb, st), "rocblas_set_stream");
+}
+
+// ------------------------------------------------------------------ solve
+void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int degree,
+                const void* V0, const void* S, double* evals, void* evecs, int64_t ldv,
+                double* resid, chase_stats* out_stats, hipStream_t st, bool* noconv) {
+  const int64_t n = h->n;
+  const int ne = h->ne, nev = h->nev;
+  const bool cplx = h->cplx;
+  const chase_opts& o = h->opts;
+  chase_stats stats{};
+  auto T0 = clk::now();
+  const int deg0 = degree + (degree & 1);
+
+  // Lanczos spectral bounds
+  const int steps = (int)std::min<int64_t>(o.lanczos_steps, n);
+  Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, nullptr, nullptr, nullptr, st);
+  auto T1 = clk::now();
+  stats.t_lanczos = secs(T0, T1);
+  const double b_sup = bd.b_sup;
+  double mu_1 = bd.mu_1, mu_ne = bd.mu_ne;
+  const double norm_est = std::max(std::fabs(bd.mu_1), std::fabs(bd.b_sup));
+
+  const bool mixed = o.filter_prec == CHASE_PREC_FP32;
+  const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 3e-6;
+  if (mixed) to_f32(cplx, H, ldh, h->H32, n, st);
+
+  CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
+  std::vector<int> m(ne, deg0);
+  std::vector<double> lam(ne, 0.0), res(ne, INFINITY), res_prev(ne, INFINITY);
+  std::vector<char> low(ne, mixed ? 1 : 0);
+  int L = 0;
+  bool converged = false;
+  std::vector<int> perm(ne);
+  FilterTiming ft64, ftlo;
+  for (int it = 0; it < o.max_iter; ++it) {
+    stats.iterations = it + 1;
+    const int ka = ne - L;
+    // ---- filter (FP64 group first, then the low-precision group)
+    auto F0 = clk::now();
+    int n64 = 0;
+    while (n64 < ka && !low[L + n64]) ++n64;
+    if (n64 > 0)
+      run_filter(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n64, &m[L], b_sup,
+                 mu_1, mu_ne, PREC_F64, false, ft64, st);
+    if (ka - n64 > 0)
+      run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
+                 &m[L + n64], b_sup, mu_1, mu_ne, PREC_F32, false, ftlo, st);
+    auto F1 = clk::now();
+    stats.t_filter += secs(F0, F1);
+    // ---- QR of [Y V]
+    qr_step(h, h->V, n, ne, L, h->W, &stats, st);
+    auto Q1 = clk::now();
+    stats.t_qr += secs(F1, Q1);
+    // ---- Rayleigh-Ritz + residuals on the active part
+    rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
+            &stats.t_resid, st);
+    check_info(h, st, "Hermitian eigensolver");
+    CHASE_HIP(hipMemcpyAsync(&lam[L], h->d_evals, ka * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> r_new(ka);
+    CHASE_HIP(hipMemcpyAsync(r_new.data(), h->d_res, ka * sizeof(double), hipMemcpyDeviceToHost,
+                             st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    for (int a = 0; a < ka; ++a) {
+      if (!std::isfinite(r_new[a]) || !std::isfinite(lam[L + a]))
+        throw Error(CHASE_ERR_NUMERIC, "non-finite Ritz value or residual");
+    }
+    // Ritz vectors come out in ascending order: the per-column history
+    // (precision flag, previous residual) no longer matches column positions,
+    // so it is carried by the smallest-residual rule: a low-precision column
+    // stays low only if it has not reached the switch threshold.
+    for (int a = 0; a < ka; ++a) {
+      res_prev[L + a] = res[L + a];
+      res[L + a] = r_new[a];
+    }
+    // ---- deflation & locking: longest converged prefix
+    int nconv = 0;
+    while (L + nconv < ne && res[L + nconv] <= tol) ++nconv;
+    L += nconv;
+    if (o.verbose) {
+      double rmax = 0;
+      for (int a = L; a < ne; ++a) rmax = std::max(rmax, res[a]);
+      std::fprintf(stderr, "chase it %d locked %d max_res %.3e mu1 %.6f mune %.6f low %d\n", it + 1,
+                   L, rmax, mu_1, mu_ne, ne - L - n64);
+    }
+    if (L >= nev) {
+      converged = true;
+      break;
+    }
+    if (it + 1 == o.max_iter) break;
+    // ---- bounds, degrees, precision groups, sort
+    mu_1 = *std::min_element(lam.begin(), lam.end());
+    mu_ne = *std::max_element(lam.begin(), lam.end());
+    const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
+    const int kb = ne - L;
+    std::vector<int> grp(kb);
+    for (int a = 0; a < kb; ++a) {
+      const int j = L + a;
+      m[j] = optimal_degree(res[j], lam[j], c, e, tol, o, deg0);
+      bool lo = mixed && res[j] > tau_sw;
+      grp[a] = lo ? 1 : 0;
+    }
+    std::vector<int> idx(kb);
+    std::iota(idx.begin(), idx.end(), 0);
+    std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) {
+      if (grp[x] != grp[y]) return grp[x] < grp[y];
+      return m[L + x] < m[L + y];
+    });
+    std::vector<int> m2(kb);
+    std::vector<double> lam2(kb), res2(kb);
+    std::vector<char> low2(kb);
+    for (int a = 0; a < kb; ++a) {
+      m2[a] = m[L + idx[a]];
+      lam2[a] = lam[L + idx[a]];
+      res2[a] = res[L + idx[a]];
+      low2[a] = (char)grp[idx[a]];
+    }
+    for (int a = 0; a < kb; ++a) {
+      m[L + a] = m2[a];
+      lam[L + a] = lam2[a];
+      res[L + a] = res2[a];
+      low[L + a] = low2[a];
+    }
+    CHASE_HIP(hipMemcpyAsync(h->d_perm, idx.data(), kb * sizeof(int), hipMemcpyHostToDevice, st));
+    gather_cols(cplx, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n, kb, h->d_perm, st);
+    copy_cols(cplx, h->W, n, off(h->V, (int64_t)L * n, h->esz), n, n, kb, st);
+  }
+  // ---- output: lowest nev of the locked pairs (or of all pairs on NOCONV)
+  const int pool = converged ? L : ne;
+  std::vector<int> idx(pool);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::stable_sort(idx.begin(), idx.end(), [&](int x, int y) { return lam[x] < lam[y]; });
+  idx.resize(nev);
+  for (int i = 0; i < nev; ++i) {
+    evals[i] = lam[idx[i]];
+    if (resid) resid[i] = res[idx[i]];
+  }
+  CHASE_HIP(hipMemcpyAsync(h->d_perm, idx.data(), nev * sizeof(int), hipMemcpyHostToDevice, st));
+  gather_cols(cplx, h->V, n, evecs, ldv, n, nev, h->d_perm, st);
+  CHASE_HIP(hipStreamSynchronize(st));
+  stats.locked = L;
+  stats.matvecs_fp64 = ft64.matvecs;
+  stats.matvecs_low = ftlo.matvecs;
+  stats.t_filter_kernels = ft64.ktime + ftlo.ktime;
+  stats.filter_launches = ft64.launches + ftlo.launches;
+  stats.filter_flops = (cplx ? 8.0 : 2.0) * (double)n * (double)n *
+                       (double)(ft64.matvecs + ftlo.matvecs);
+  stats.b_sup = b_sup;
+  stats.mu_1 = mu_1;
+  stats.mu_ne = mu_ne;
+  stats.t_all = secs(T0, clk::now());
+  if (out_stats) *out_stats = stats;
+  *noconv = !converged;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+void chase_default_opts(chase_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->max_deg = 36;
+  o->deg_extra = 2;
+  o->optimize_degree = 1;
+  o->lanczos_steps = 25;
+  o->lanczos_vecs = 4;
+  o->max_iter = 50;
+  o->filter_prec = CHASE_PREC_FP64;
+  o->switch_tol = 0.0;
+  o->verbose = 0;
+}
+
+size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex, const chase_opts* opts) {
+  if (n < 1 || nev < 1 || nex < 1 || (int64_t)nev + nex > n) return 0;
+  if (dtype != CHASE_C128 && dtype != CHASE_F64) return 0;
+  chase_opts o;
+  chase_default_opts(&o);
+  if (opts) o = *opts;
+  return sizes(dtype, n, nev, nex, o).total;
+}
+
+const char* chase_last_error(void) { return g_last_error.c_str(); }
+
+chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int nev, int nex,
+                          const chase_opts* opts) {
+  chase_handle_s* h = nullptr;
+  chase_status st = guarded([&] {
+    CHASE_REQUIRE(out != nullptr, "handle pointer is NULL");
+    *out = nullptr;
+    CHASE_REQUIRE(dtype == CHASE_C128 || dtype == CHASE_F64, "unknown dtype");
+    CHASE_REQUIRE(n >= 1 && nev >= 1 && nex >= 1, "need n >= 1, nev >= 1, nex >= 1");
+    CHASE_REQUIRE((int64_t)nev + nex <= n, "nev + nex must not exceed n");
+    chase_opts o;
+    chase_default_opts(&o);
+    if (opts) o = *opts;
+    validate_opts(o);
+    h = new chase_handle_s();
+    h->dtype = dtype;
+    h->cplx = dtype == CHASE_C128;
+    h->n = n;
+    h->nev = nev;
+    h->nex = nex;
+    h->ne = nev + nex;
+    h->opts = o;
+    h->esz = h->cplx ? 16 : 8;
+    CHASE_HIP(hipGetDevice(&h->device));
+    const Sizes sz = sizes(dtype, n, nev, nex, o);
+    size_t fr = 0, tot = 0;
+    CHASE_HIP(hipMemGetInfo(&fr, &tot));
+    if (sz.total > fr)
+      throw Error(CHASE_ERR_NOMEM, "workspace of " + std::to_string(sz.total) +
+                                       " bytes exceeds free device memory (" +
+                                       std::to_string(fr) + ")");
+    const int64_t ne = h->ne;
+    h->V = dev_alloc(h, (size_t)n * ne * h->esz);
+    h->W = dev_alloc(h, (size_t)n * ne * h->esz);
+    h->Z = dev_alloc(h, (size_t)n * ne * h->esz);
+    h->G = dev_alloc(h, (size_t)ne * ne * h->esz);
+    h->R = dev_alloc(h, (size_t)ne * ne * h->esz);
+    h->ws_elems = splitk_ws_elems((int)ne);
+    h->ws = dev_alloc(h, h->ws_elems * h->esz);
+    h->d_scale = static_cast<double*>(dev_alloc(h, ne * 8));
+    h->d_evals = static_cast<double*>(dev_alloc(h, ne * 8));
+    h->d_res = static_cast<double*>(dev_alloc(h, ne * 8));
+    h->d_E = static_cast<double*>(dev_alloc(h, ne * 8));
+    h->d_g = static_cast<double*>(dev_alloc(h, ne * 8));
+    h->d_partial = static_cast<double*>(dev_alloc(h, (size_t)gemm_row_tiles(n) * ne * 8));
+    h->d_flags = static_cast<int*>(dev_alloc(h, 64));
+    h->d_info = static_cast<int*>(dev_alloc(h, 64));
+    h->d_perm = static_cast<int*>(dev_alloc(h, ne * 4));
+    h->tau = dev_alloc(h, ne * h->esz);
+    const int W = h->cplx ? 2 : 1;
+    const int nv = o.lanczos_vecs, steps = o.lanczos_steps;
+    lanczos_bytes(h->cplx, n, nv, steps, &h->lz.max_splits);
+    h->lz.q_prev = dev_alloc(h, (size_t)n * nv * W * 8);
+    h->lz.q_cur = dev_alloc(h, (size_t)n * nv * W * 8);
+    h->lz.w = dev_alloc(h, (size_t)n * nv * W * 8);
+    h->lz.wpart = dev_alloc(h, (size_t)h->lz.max_splits * nv * n * W * 8);
+    h->lz.dotp = static_cast<double*>(dev_alloc(h, 128 * nv * 8));
+    h->lz.nrmp = static_cast<double*>(dev_alloc(h, 128 * nv * 8));
+    h->lz.alpha = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
+    h->lz.beta = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
+    if (o.filter_prec == CHASE_PREC_FP32) h->H32 = dev_alloc(h, (size_t)n * n * h->esz / 2);
+    rb_check(rocblas_create_handle(&h->rb), "rocblas_create_handle");
+    *out = h;
+  });
+  if (st != CHASE_OK && h) chase_destroy(h);
+  return st;
+}
+
+void chase_destroy(chase_handle_t h) {
+  if (!h) return;
+  (void)hipSetDevice(h->device);
+  (void)hipDeviceSynchronize();
+  for (void* p : h->allocs) (void)hipFree(p);
+  if (h->tape) (void)hipFree(h->tape);
+  for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
+  if (h->rb) rocblas_destroy_handle(h->rb);
+  delete h;
+}
+
+chase_status chase_solve(chase_handle_t h, const void* H, int64_t ldh, double tol, int degree,
+                         const void* V0, const void* S, double* evals_host, void* evecs_dev,
+                         int64_t ldv, double* resid_host, chase_stats* stats, void* stream) {
+  bool noconv = false;
+  chase_status s = guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && V0 && S && evals_host && evecs_dev, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n && ldv >= h->n, "leading dimension smaller than n");
+    CHASE_REQUIRE(tol > 0 && std::isfinite(tol), "tol must be positive");
+    CHASE_REQUIRE(degree >= 2 && degree <= h->opts.max_deg + 1, "degree out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    solve_impl(h, H, ldh, tol, degree, V0, S, evals_host, evecs_dev, ldv, resid_host, stats, st,
+               &noconv);
+  });
+  if (s == CHASE_OK && noconv) {
+    g_last_error = "maximum number of iterations reached";
+    return CHASE_ERR_NOCONV;
+  }
+  return s;
+}
+
+chase_status chase_lanczos(chase_handle_t h, const void* H, int64_t ldh, const void* S, int nvec,
+                           int steps, double* b_sup, double* mu_1, double* mu_ne,
+                           double* alpha_host, double* beta_host, int* steps_host, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && S, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n, "ldh < n");
+    CHASE_REQUIRE(nvec >= 1 && nvec <= h->opts.lanczos_vecs, "nvec out of range");
+    CHASE_REQUIRE(steps >= 1 && steps <= h->opts.lanczos_steps && steps <= h->n,
+                  "steps out of range");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    std::vector<double> a, b;
+    std::vector<int> lens;
+    Bounds bd = do_lanczos(h, H, ldh, S, nvec, steps, &a, &b, &lens, st);
+    if (b_sup) *b_sup = bd.b_sup;
+    if (mu_1) *mu_1 = bd.mu_1;
+    if (mu_ne) *mu_ne = bd.mu_ne;
+    for (int r = 0; r < nvec; ++r)
+      for (int j = 0; j < steps; ++j) {
+        if (alpha_host) alpha_host[(size_t)r * steps + j] = a[(size_t)j * nvec + r];
+        if (beta_host) beta_host[(size_t)r * steps + j] = b[(size_t)j * nvec + r];
+      }
+    if (steps_host)
+      for (int r = 0; r < nvec; ++r) steps_host[r] = lens[r];
+  });
+}
+
+chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X, int64_t ldx, int k,
+                          const int* degrees, double b_sup, double mu_1, double mu_ne, int prec,
+                          int record_tape, int64_t* matvecs, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && X && degrees, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n && ldx >= h->n, "leading dimension smaller than n");
+    CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32, "unknown precision");
+    CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
+                      mu_1 < mu_ne && mu_ne < b_sup,
+                  "need mu_1 < mu_ne < b_sup");
+    for (int a = 0; a < k; ++a) {
+      CHASE_REQUIRE(degrees[a] >= 2 && degrees[a] % 2 == 0 && degrees[a] <= 1000,
+                    "degrees must be even and in [2, 1000]");
+      CHASE_REQUIRE(a == 0 || degrees[a] >= degrees[a - 1], "degrees must be non-decreasing");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    if (record_tape) ensure_tape(h, k, degrees[k - 1]);
+    if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
+    FilterTiming ft;
+    h->tape_valid = false;
+    run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne,
+               prec == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64, record_tape != 0, ft, st);
+    if (matvecs) *matvecs = ft.matvecs;
+  });
+}
+
+chase_status chase_qr(chase_handle_t h, void* X, int64_t ldx, int k, int locked, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(X != nullptr, "NULL pointer argument");
+    CHASE_REQUIRE(ldx >= h->n, "ldx < n");
+    CHASE_REQUIRE(k >= 1 && k <= h->ne && locked >= 0 && locked < k, "bad k / locked");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    qr_step(h, X, ldx, k, locked, h->W, nullptr, st);
+    CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+chase_status chase_rayleigh_ritz(chase_handle_t h, const void* H, int64_t ldh, void* Q, int64_t ldq,
+                                 int k, double norm_scale, double* ritz, double* resid,
+                                 void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && Q && ritz, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n && ldq >= h->n, "leading dimension smaller than n");
+    CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
+    CHASE_REQUIRE(norm_scale > 0, "norm_scale must be positive");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    rr_step(h, H, ldh, Q, ldq, k, norm_scale, h->W, h->Z, nullptr, nullptr, st);
+    check_info(h, st, "Hermitian eigensolver");
+    CHASE_HIP(hipMemcpyAsync(ritz, h->d_evals, k * 8, hipMemcpyDeviceToHost, st));
+    if (resid) CHASE_HIP(hipMemcpyAsync(resid, h->d_res, k * 8, hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+chase_status chase_eigval_adjoint(chase_handle_t h, const void* V, int64_t ldv, int m,
+                                  const double* g_host, void* dH, int64_t ldd, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(V && g_host && dH, "NULL pointer argument");
+    CHASE_REQUIRE(ldv >= h->n && ldd >= h->n, "leading dimension smaller than n");
+    CHASE_REQUIRE(m >= 1 && m <= h->ne, "m must be in [1, nev+nex]");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    const int64_t n = h->n;
+    // Z = V diag(g); dH += Z V^H
+    copy_cols(h->cplx, V, ldv, h->Z, n, n, m, st);
+    CHASE_HIP(hipMemcpyAsync(h->d_g, g_host, m * 8, hipMemcpyHostToDevice, st));
+    scale_cols(h->cplx, h->Z, n, n, m, h->d_g, st);
+    GemmArgs g = gargs(n, n, m, h->Z, n, V, ldv, dH, ldd);
+    g.beta = 1.0;
+    gemm(h->cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g, st);
+    CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+chase_status chase_filter_adjoint(chase_handle_t h, const void* H, int64_t ldh, const void* gY,
+                                  int64_t ldg, void* dH, int64_t ldd, void* gX, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && gY && dH, "NULL pointer argument");
+    CHASE_REQUIRE(h->tape_valid, "no recorded filter tape (call chase_filter with record_tape=1)");
+    CHASE_REQUIRE(ldh >= h->n && ldg >= h->n && ldd >= h->n, "leading dimension smaller than n");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    const int64_t n = h->n;
+    const int k = h->tape_k;
+    const std::vector<int>& deg = h->tape_deg;
+    const int mmax = deg[k - 1];
+    const std::vector<Coef>& cf = h->tape_coef;
+    // Reverse sweep of X_s = a_s (H - c) X_{s-1} + b_s X_{s-2}, s = 1..m_a:
+    //   Gb_{s-1} += a_s (H - c) Gb_s ; Gb_{s-2} += b_s Gb_s ; dH += a_s Gb_s X_{s-1}^H
+    // Column a enters the sweep at s = m_a with Gb = gY.  Buffers (n x k):
+    //   G1 = Gb_s, G0 = Gb_{s-1}, with G2 accumulating Gb_{s-2} and rotated.
+    void* G1 = h->V;
+    void* G0 = h->W;
+    void* G2 = h->Z;
+    const size_t bytes = (size_t)n * k * h->esz;
+    fill_zero(G1, bytes, st);
+    fill_zero(G0, bytes, st);
+    fill_zero(G2, bytes, st);
+    // columns with m_a == mmax start at s = mmax
+    auto first_col = [&](int s) { return (int)(std::lower_bound(deg.begin(), deg.end(), s) - deg.begin()); };
+    for (int s = mmax; s >= 1; --s) {
+      // inject gY for columns whose degree is exactly s: they start here
+      const int a_lo = first_col(s), a_hi = first_col(s + 1);
+      if (a_hi > a_lo)
+        copy_cols(h->cplx, off(const_cast<void*>(gY), (int64_t)a_lo * ldg, h->esz), ldg,
+                  off(G1, (int64_t)a_lo * n, h->esz), n, n, a_hi - a_lo, st);
+      const int a0 = a_lo;  // active columns at step s: degree >= s
+      const int cols = k - a0;
+      if (cols <= 0) continue;
+      const Coef c = cf[s - 1];
+      void* g1 = off(G1, (int64_t)a0 * n, h->esz);
+      // dH += a_s Gb_s X_{s-1}^H  (X_{s-1} from tape slot s-1)
+      {
+        GemmArgs g = gargs(n, n, cols, g1, n, off(h->tape, ((int64_t)(s - 1) * k + a0) * n, h->esz),
+                           n, dH, ldd);
+        g.alpha = c.alpha;
+        g.beta = 1.0;
+        gemm(h->cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g, st);
+      }
+      // Gb_{s-1} += a_s (H - c) Gb_s   (EPI_CHEB with beta = 1 accumulates)
+      {
+        GemmArgs g = gargs(n, cols, n, H, ldh, g1, n, off(G0, (int64_t)a0 * n, h->esz), n);
+        g.alpha = c.alpha;
+        g.gamma = c.gamma;
+        g.beta = 1.0;
+        gemm(h->cplx, PREC_F64, OP_N, OP_N, EPI_CHEB, g, st);
+      }
+      // Gb_{s-2} += b_s Gb_s
+      if (c.beta != 0.0)
+        axpy_cols(h->cplx, c.beta, g1, n, off(G2, (int64_t)a0 * n, h->esz), n, n, cols, st);
+      // rotate: Gb_{s-1} becomes the current, Gb_{s-2} the next accumulator
+      std::swap(G1, G0);  // G1 = Gb_{s-1}
+      std::swap(G0, G2);  // G0 = Gb_{s-2}, G2 = old Gb_s (to be cleared)
+      fill_zero(off(G2, (int64_t)a0 * n, h->esz), (size_t)n * cols * h->esz, st);
+    }
+    // G1 now holds Gb_0 = dL/dX_0
+    if (gX) copy_cols(h->cplx, G1, n, gX, ldg, n, k, st);
+    herm_part(h->cplx, dH, ldd, n, st);
+    CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,88 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol the
+header declares, validates arguments before touching a GPU, and sizes its
+workspace consistently with the paper's one-GPU memory estimate."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "chase.h")
+
+
+def _lib():
+    import paper_2205_02491_amd as pk
+    if not os.path.exists(pk.LIB_PATH):
+        pk.build_lib = __import__("paper_2205_02491_amd.build", fromlist=["build"])
+        pk.build_lib.build()
+    return pk
+
+
+def header_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(chase_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    pk = _lib()
+    L = pk.lib()
+    names = header_functions()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(L, name), name
+    assert sorted(pk.EXPORTED) == names
+
+
+def test_default_opts():
+    pk = _lib()
+    o = pk.default_opts()
+    assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
+            o.max_iter, o.filter_prec) == (36, 2, 1, 25, 4, 50, 0)
+
+
+def test_workspace_bytes_matches_one_gpu_memory_estimate():
+    """Eq. (7) with a single GPU and a single rank (p = q = n, r_g = c_g = 1)
+    gives n^2 + 3 n n_e + (2n + n_e) n_e elements, n^2 of which is the
+    caller's matrix.  The library keeps three n x n_e blocks and two
+    n_e x n_e matrices plus small buffers: it must stay within the estimate's
+    non-matrix part plus the split-K workspace and Lanczos buffers, and
+    grow linearly in n at fixed n_e."""
+    pk = _lib()
+    for n, nev, nex in [(1000, 100, 40), (20000, 1000, 300), (30000, 1500, 500)]:
+        ne = nev + nex
+        b = pk.chase_workspace_bytes(n, nev, nex, cplx=True)
+        eq7_rest = (3 * n * ne + (2 * n + ne) * ne) * 16
+        assert 3 * n * ne * 16 <= b <= eq7_rest + 400 * 2**20, (n, b, eq7_rest)
+        b_real = pk.chase_workspace_bytes(n, nev, nex, cplx=False)
+        assert b_real < b
+    o = pk.default_opts(filter_prec=1)
+    assert pk.chase_workspace_bytes(20000, 1000, 300, opts=o) >= 20000 ** 2 * 8
+    assert pk.chase_workspace_bytes(10, 8, 4) == 0      # nev + nex > n
+    assert pk.chase_workspace_bytes(10, 0, 4) == 0
+
+
+def test_create_rejects_bad_sizes_without_gpu():
+    pk = _lib()
+    L = pk.lib()
+    h = ctypes.c_void_p()
+    st = L.chase_create(ctypes.byref(h), 0, 10, 8, 4, None)
+    assert st == pk.ERR_ARG
+    assert b"nev + nex" in L.chase_last_error()
+    st = L.chase_create(ctypes.byref(h), 7, 10, 2, 2, None)
+    assert st == pk.ERR_ARG
+    o = pk.default_opts(lanczos_vecs=9)
+    st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
+    assert st == pk.ERR_ARG
+    assert L.chase_solve(None, None, 0, 0.0, 0, None, None, None, None, 0, None, None,
+                         None) == pk.ERR_ARG
+    assert L.chase_filter_adjoint(None, None, 0, None, 0, None, 0, None, None) == pk.ERR_ARG
+
+
+def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
+    import paper_2205_02491_amd as pk
+    monkeypatch.setattr(pk, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(pk, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        pk.lib()

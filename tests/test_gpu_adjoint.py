@@ -1,0 +1,146 @@
+"""Hand-written adjoints (through the C ABI) against central finite
+differences and closed-form reference gradients.
+
+Eigenvalue loss: dL/dH = sum_i w_i v_i v_i^H (first-order perturbation of
+simple eigenvalues), referenced by the planted eigenvectors.
+Filtered-block loss L = ||Y^H B||_F^2 with Y = p(H) X0 at frozen bounds and
+degrees: referenced by the Daleckii-Krein formula
+G = Q (F o (Q^H dL/dY X0^H Q)) Q^H, F_ij = (p_i - p_j)/(l_i - l_j), F_ii = p'(l_i).
+Target: 1e-6 relative."""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import announce, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2205_02491_amd as pk
+    pk.lib()
+    return pk
+
+
+def herm_dir(n, cplx, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    e = gen.gaussian(g, (n, n), cplx)
+    e = (e + e.conj().T) / 2
+    return e / np.linalg.norm(e)
+
+
+def directional(G, E):
+    return float(np.real(np.sum(np.conj(G) * E)))
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_eigval_adjoint_fd_and_reference(pk, cplx):
+    import torch
+    announce(f"eigval adjoint n=300 cplx={cplx}")
+    p = gen.make_uniform(n=300, nev=12, nex=8, cplx=cplx, cfg=30)
+    w = np.random.Generator(np.random.PCG64(31)).standard_normal(p.nev)
+    V0, S = to_gpu(p.V0), to_gpu(p.S)
+
+    def loss(Hn):
+        lam, _ = pk.chase_eigh(to_gpu(Hn), p.nev, p.nex, 1e-12, 20, V0, S)
+        return float(np.dot(w, to_np(lam)))
+
+    H = to_gpu(p.H).requires_grad_(True)
+    lam, vec = pk.chase_eigh(H, p.nev, p.nex, 1e-12, 20, V0, S)
+    (torch.from_numpy(w).cuda() * lam).sum().backward()
+    G = to_np(H.grad)
+    q = p.Q[:, : p.nev]
+    G_ref = (q * w[None, :]) @ q.conj().T
+    assert np.linalg.norm(G - G_ref) <= 1e-8 * np.linalg.norm(G_ref)
+    h = 1e-6
+    for s in range(3):
+        E = herm_dir(300, cplx, 40 + s)
+        fd = (loss(p.H + h * E) - loss(p.H - h * E)) / (2 * h)
+        an = directional(G, E)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), np.linalg.norm(G) * 1e-3), (fd, an)
+
+
+def _cheb_deriv(lam, m, b_sup, mu_1, mu_ne):
+    hstep = 1e-5 * (b_sup - mu_1)
+    return (oracle.cheb_poly_value(lam + hstep, m, b_sup, mu_1, mu_ne)
+            - oracle.cheb_poly_value(lam - hstep, m, b_sup, mu_1, mu_ne)) / (2 * hstep)
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_filter_adjoint_fd_and_daleckii_krein(pk, cplx):
+    import torch
+    announce(f"filter adjoint n=260 cplx={cplx}")
+    n, k, m = 260, 24, 10
+    g = np.random.Generator(np.random.PCG64(50 + cplx))
+    lam = gen.spectrum_uniform_iid(n, g)
+    q = gen.haar(n, g, cplx)
+    Hn = gen.planted(lam, q)
+    X0 = gen.gaussian(g, (n, k), cplx)
+    B = gen.gaussian(g, (n, 5), cplx)
+    b_sup, mu_1, mu_ne = 1.05, -1.0, -0.5
+    deg = np.full(k, m, dtype=np.int32)
+    Bt = to_gpu(B)
+
+    def loss_np(Hm):
+        y, _ = oracle.chebyshev_filter(Hm, X0, deg, b_sup, mu_1, mu_ne)
+        return float(np.linalg.norm(y.conj().T @ B) ** 2)
+
+    H = to_gpu(Hn).requires_grad_(True)
+    Y = pk.filtered_block(H, to_gpu(X0), deg, b_sup, mu_1, mu_ne)
+    L = (torch.linalg.matrix_norm(Y.mH @ Bt) ** 2)
+    L.backward()
+    G = to_np(H.grad)
+    # Daleckii-Krein reference
+    pv = oracle.cheb_poly_value(lam, m, b_sup, mu_1, mu_ne)
+    dp = _cheb_deriv(lam, m, b_sup, mu_1, mu_ne)
+    dl = lam[:, None] - lam[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = np.where(np.abs(dl) > 1e-9, (pv[:, None] - pv[None, :]) / dl, 0.0)
+    F[np.diag_indices(n)] = dp
+    Y_ref, _ = oracle.chebyshev_filter(Hn, X0, deg, b_sup, mu_1, mu_ne)
+    gY = 2 * B @ (B.conj().T @ Y_ref)
+    G_ref = q @ (F * (q.conj().T @ gY @ X0.conj().T @ q)) @ q.conj().T
+    G_ref = (G_ref + G_ref.conj().T) / 2
+    assert np.linalg.norm(G - G_ref) <= 1e-6 * np.linalg.norm(G_ref)
+    h = 1e-6
+    for s in range(3):
+        E = herm_dir(n, cplx, 60 + s)
+        fd = (loss_np(Hn + h * E) - loss_np(Hn - h * E)) / (2 * h)
+        an = directional(G, E)
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * np.linalg.norm(G), (fd, an)
+
+
+def test_filter_adjoint_mixed_degrees_input_gradient(pk):
+    """Per-column degrees (sorted) and the gradient w.r.t. the filter input:
+    Y = P X0 column-wise with P_a = p_{m_a}(H), so dL/dx_a = P_a^H g_a =
+    p_{m_a}(H) g_a (p real, H Hermitian) -- the filter itself applied to gY."""
+    import torch
+    announce("filter adjoint per-column degrees + input gradient")
+    n, k = 300, 16
+    g = np.random.Generator(np.random.PCG64(70))
+    lam = gen.spectrum_uniform_iid(n, g)
+    q = gen.haar(n, g, True)
+    Hn = gen.planted(lam, q)
+    X0 = gen.gaussian(g, (n, k), True)
+    deg = np.sort(2 * g.integers(1, 8, size=k)).astype(np.int32)
+    b_sup, mu_1, mu_ne = 1.02, -1.0, -0.4
+    gY = gen.gaussian(g, (n, k), True)
+    H = to_gpu(Hn).requires_grad_(True)
+    X = to_gpu(X0).requires_grad_(True)
+    Y = pk.filtered_block(H, X, deg, b_sup, mu_1, mu_ne)
+    torch.sum(torch.real(torch.conj(to_gpu(gY)) * Y)).backward()
+    gx_ref, _ = oracle.chebyshev_filter(Hn, gY, deg, b_sup, mu_1, mu_ne)
+    assert np.linalg.norm(to_np(X.grad) - gx_ref) <= 1e-10 * np.linalg.norm(gx_ref)
+    # dH by FD on the linear functional
+    Gd = to_np(H.grad)
+    for s in range(2):
+        E = herm_dir(n, True, 80 + s)
+        yp, _ = oracle.chebyshev_filter(Hn + 1e-6 * E, X0, deg, b_sup, mu_1, mu_ne)
+        ym, _ = oracle.chebyshev_filter(Hn - 1e-6 * E, X0, deg, b_sup, mu_1, mu_ne)
+        fd = float(np.real(np.sum(np.conj(gY) * (yp - ym)))) / 2e-6
+        an = directional(Gd, E)
+        assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * np.linalg.norm(Gd), (fd, an)

@@ -1,0 +1,128 @@
+"""End-to-end parity of chase_solve (HIP path, C ABI) with the CPU oracle.
+
+Bar (the method's accuracy targets): eigenvalues within 1e-10 * ||H|| of
+the oracle's, iteration counts within one, residuals <= tol, orthonormal
+eigenvectors (||V^H V - I|| <= 1e-12) spanning the oracle's subspace within
+the Davis-Kahan bound ||R||_F / gap (and 1e-8 where that bound allows)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import announce, subspace_sin, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2205_02491_amd as pk
+    pk.lib()
+    return pk
+
+
+def _check_against_oracle(pk, p, opts=None, it_tol=1, ev_tol=1e-10):
+    ev_o, v_o, r_o, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
+    H = to_gpu(p.H)
+    ev, vec, res, st = pk.chase_solve(H, p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0), to_gpu(p.S),
+                                      opts=opts)
+    assert st["converged"]
+    v = to_np(vec)
+    norm = max(abs(p.lam[0]), abs(p.lam[-1]))
+    assert np.max(np.abs(ev - ev_o)) <= ev_tol * norm, np.max(np.abs(ev - ev_o))
+    assert np.max(np.abs(ev - p.lam[: p.nev])) <= 2 * p.tol * norm
+    assert abs(st["iterations"] - st_o.iterations) <= it_tol, (st["iterations"], st_o.iterations)
+    assert np.all(res <= p.tol)
+    assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) <= 1e-12
+    r = p.H @ v - v * ev[None, :]
+    assert np.max(np.linalg.norm(r, axis=0)) <= 1.01 * p.tol * max(abs(st["mu_1"]), abs(st["b_sup"]),
+                                                                   norm)
+    gap = p.lam[p.nev] - p.lam[p.nev - 1]
+    bound = (np.linalg.norm(r) + np.linalg.norm(p.H @ v_o - v_o * ev_o[None, :])) / gap
+    ang = subspace_sin(v, v_o)
+    assert ang <= max(2 * bound, 1e-8), (ang, bound)
+    return ev, v, st, st_o
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_solve_small_uniform_matches_oracle(pk, cplx):
+    announce(f"solve n=1000 nev=100 nex=40 cplx={cplx}")
+    p = gen.make_uniform(n=1000, nev=100, nex=40, cplx=cplx)
+    ev, v, st, st_o = _check_against_oracle(pk, p)
+    # matvec count parity (deterministic convergence of the filter)
+    if st["iterations"] == st_o.iterations:
+        assert abs(st["matvecs_fp64"] - st_o.matvecs) <= 0.02 * st_o.matvecs
+
+
+def test_solve_golden_counts(pk):
+    """Iterations / Matvecs against the oracle's recorded counts."""
+    announce("solve n=1000 golden counts")
+    with open(os.path.join(GOLDEN, "oracle_uniform1000.json")) as f:
+        gold = json.load(f)
+    p = gen.make_uniform(n=1000, nev=100, nex=40)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S))
+    assert abs(st["iterations"] - gold["iterations"]) <= 1
+    np.testing.assert_allclose(ev, np.array(gold["evals"]), atol=1e-10)
+
+
+def test_solve_geometric_cluster(pk):
+    announce("solve geometric n=2000 nev=100 nex=30")
+    p = gen.make_geometric(n=2000, nev=100, nex=30, cfg=11)
+    _check_against_oracle(pk, p)
+
+
+def test_solve_conjugate_frame_non_real(pk):
+    """Row-major torch H vs column-major library: the returned vectors must
+    be eigenvectors of H itself (not of conj(H))."""
+    announce("solve non-real H frame check")
+    p = gen.make_uniform(n=400, nev=20, nex=10, cfg=12)
+    assert np.max(np.abs(p.H.imag)) > 0.01
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S))
+    v = to_np(vec)
+    r = p.H @ v - v * ev[None, :]
+    assert np.max(np.linalg.norm(r, axis=0)) < 1e-9
+    assert subspace_sin(v, p.Q[:, :20]) < 1e-8
+
+
+def test_solve_tiny_edge(pk):
+    """Smallest legal sizes: nev=1, nex=1, n=3 (single tile, ragged in every
+    direction)."""
+    announce("solve tiny n=3")
+    g = np.random.Generator(np.random.PCG64(3))
+    a = gen.gaussian(g, (3, 3), True)
+    h = (a + a.conj().T) / 2
+    v0 = gen.gaussian(g, (3, 2), True)
+    s = gen.gaussian(g, (3, 4), True)
+    ev, vec, res, st = pk.chase_solve(to_gpu(h), 1, 1, 1e-10, 4, to_gpu(v0), to_gpu(s))
+    w = np.linalg.eigvalsh(h)
+    assert abs(ev[0] - w[0]) < 1e-10 * np.max(np.abs(w))
+
+
+def test_solve_noconv_returns_partial(pk):
+    announce("solve noconv")
+    p = gen.make_uniform(n=300, nev=20, nex=10, cfg=13)
+    o = pk.default_opts(max_iter=2)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, 1e-30, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S), opts=o)
+    assert not st["converged"] and st["iterations"] == 2
+    assert np.all(np.diff(ev) >= 0)
+    assert np.max(np.abs(ev - p.lam[:20])) < 1e-3
+
+
+def test_solve_rejects_nan(pk):
+    announce("solve NaN input")
+    p = gen.make_uniform(n=200, nev=10, nex=6, cfg=14)
+    h = p.H.copy()
+    h[3, 5] = np.nan
+    with pytest.raises(pk.ChaseError) as e:
+        pk.chase_solve(to_gpu(h), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0), to_gpu(p.S))
+    assert e.value.status == pk.ERR_NUMERIC

@@ -1,0 +1,135 @@
+"""Per-step parity of the HIP path with the CPU oracle (through the C ABI)."""
+import math
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import announce, rel_err, subspace_sin, to_gpu, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pk():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2205_02491_amd as pk
+    pk.lib()
+    return pk
+
+
+def _problem(n, cplx, seed):
+    g = np.random.Generator(np.random.PCG64(seed))
+    lam = gen.spectrum_uniform_iid(n, g)
+    q = gen.haar(n, g, cplx)
+    return gen.planted(lam, q), lam, q, g
+
+
+# ------------------------------------------------------------------ filter
+@pytest.mark.parametrize("cplx", [True, False])
+@pytest.mark.parametrize("n,k", [(300, 37), (700, 150), (1000, 140)])
+def test_filter_matches_oracle(pk, cplx, n, k):
+    announce(f"filter parity n={n} k={k} cplx={cplx}")
+    h, lam, q, g = _problem(n, cplx, 1000 + n + k)
+    x = gen.gaussian(g, (n, k), cplx)
+    deg = np.sort(2 * g.integers(1, 11, size=k)).astype(np.int32)
+    b_sup, mu_1, mu_ne = 1.03, -1.0, -0.55
+    y_ref, mv_ref = oracle.chebyshev_filter(h, x, deg, b_sup, mu_1, mu_ne)
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne)
+    assert mv == mv_ref
+    y = to_np(y)
+    for a in range(k):
+        err = np.max(np.abs(y[:, a] - y_ref[:, a])) / np.max(np.abs(y_ref[:, a]))
+        assert err < 1e-12, (a, deg[a], err)
+
+
+def test_filter_closed_form_diagonal(pk):
+    announce("filter closed form on diag(lambda)")
+    n, k = 513, 19
+    lam = np.sort(np.random.Generator(np.random.PCG64(5)).uniform(-1, 1, n))
+    x = np.random.Generator(np.random.PCG64(6)).standard_normal((n, k)) + 0j
+    deg = np.full(k, 20, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 1.01, -1.0, -0.7
+    y, _ = pk.chase_filter(to_gpu(np.diag(lam).astype(complex)), to_gpu(x), deg, b_sup, mu_1, mu_ne)
+    p = oracle.cheb_poly_value(lam, 20, b_sup, mu_1, mu_ne)
+    ref = p[:, None] * x
+    assert rel_err(to_np(y), ref) < 1e-12
+
+
+def test_filter_fp32_error_bound(pk):
+    """Low-precision products: each step's error is bounded by ~ gamma_n of
+    FP32 times ||H|| ||X||; over m steps of a bounded recurrence the relative
+    error stays at a few 1e-6."""
+    announce("filter fp32 error bound")
+    n, k = 800, 64
+    h, lam, q, g = _problem(n, True, 77)
+    x = gen.gaussian(g, (n, k), True)
+    deg = np.full(k, 8, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 1.02, -1.0, -0.6
+    y_ref, _ = oracle.chebyshev_filter(h, x, deg, b_sup, mu_1, mu_ne)
+    y, _ = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_FP32)
+    err = rel_err(to_np(y), y_ref)
+    assert 1e-9 < err < 5e-5, err
+
+
+# ------------------------------------------------------------------ Lanczos
+@pytest.mark.parametrize("cplx", [True, False])
+def test_lanczos_matches_oracle(pk, cplx):
+    announce(f"lanczos parity cplx={cplx}")
+    n = 900
+    h, lam, q, g = _problem(n, cplx, 31 + cplx)
+    s = gen.gaussian(g, (n, 4), cplx)
+    runs = oracle.lanczos_runs(h, s, 25)
+    b_ref, m1_ref, mne_ref, _ = oracle.spectral_bounds(h, s, 25, 120)
+    handle = pk.Handle(n, 80, 40, to_gpu(h).dtype)
+    b_sup, mu_1, mu_ne, a, b, lens = pk.chase_lanczos(to_gpu(h), to_gpu(s), 25, handle=handle)
+    for r, (ar, br) in enumerate(runs):
+        assert lens[r] == len(ar)
+        np.testing.assert_allclose(a[r, : len(ar)], ar, atol=1e-11)
+        np.testing.assert_allclose(b[r, : len(br)], br, atol=1e-11)
+    assert abs(b_sup - b_ref) < 1e-11 and abs(mu_1 - m1_ref) < 1e-11
+    assert abs(mu_ne - mne_ref) < 1e-9
+    assert b_sup >= lam[-1] - 1e-12 and mu_1 >= lam[0] - 1e-12
+
+
+# ------------------------------------------------------------------ QR
+@pytest.mark.parametrize("locked", [0, 7])
+def test_qr_invariants_and_span(pk, locked):
+    announce(f"qr locked={locked}")
+    n, k = 1100, 150
+    g = np.random.Generator(np.random.PCG64(41))
+    y = gen.haar(n, g, True)[:, :locked] if locked else np.zeros((n, 0), complex)
+    base = gen.gaussian(g, (n, k - locked), True)
+    # columns with widely different scales and a near-dependency
+    v = base * np.logspace(0, 6, k - locked)[None, :]
+    v[:, 1] = v[:, 0] * 1e-3 + 1e-9 * base[:, 1]
+    x = np.concatenate([y, v], axis=1)
+    qd = to_np(pk.chase_qr(to_gpu(x), locked))
+    assert np.array_equal(qd[:, :locked], y)
+    assert np.linalg.norm(qd.conj().T @ qd - np.eye(k)) < 1e-12 * math.sqrt(k)
+    q_ref = oracle.qr_locked(y, v)
+    # same span: projector difference
+    pdiff = qd @ qd.conj().T - q_ref @ q_ref.conj().T
+    assert np.linalg.norm(pdiff, 2) < 1e-8
+
+
+# ------------------------------------------------------------------ RR + residual
+@pytest.mark.parametrize("cplx", [True, False])
+def test_rayleigh_ritz_matches_oracle(pk, cplx):
+    announce(f"rayleigh-ritz cplx={cplx}")
+    n, k = 1000, 140
+    h, lam, q, g = _problem(n, cplx, 51 + cplx)
+    qa, _ = np.linalg.qr(gen.gaussian(g, (n, k), cplx) + q[:, :k] * 5)
+    th_ref, va_ref = oracle.rayleigh_ritz(h, qa)
+    r_ref = oracle.residual_norms(h, va_ref, th_ref, 1.3)
+    th, va, res = pk.chase_rayleigh_ritz(to_gpu(h), to_gpu(qa), 1.3)
+    np.testing.assert_allclose(th, th_ref, atol=1e-13)
+    np.testing.assert_allclose(res, r_ref, rtol=1e-8, atol=1e-14)
+    va = to_np(va)
+    # Ritz vectors agree up to a phase per (simple) column
+    ov = np.abs(np.sum(va.conj() * va_ref, axis=0))
+    gaps = np.minimum(np.diff(th_ref, prepend=-np.inf), np.diff(th_ref, append=np.inf))
+    ok = gaps > 1e-6
+    np.testing.assert_allclose(ov[ok], 1.0, atol=1e-8)
