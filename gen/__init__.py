@@ -229,3 +229,60 @@ def make_torch(kind: str, n: int, nev: int, nex: int, device="cuda", cplx=True,
     gs.manual_seed(BASE_SEED + 10 * cfg + SLOT_S)
     s = torch.randn((n, n_lanczos), generator=gs, dtype=dt, device=device)
     return dict(H=h, lam=lam, V0=v0, S=s, nev=nev, nex=nex, deg=deg, tol=tol)
+
+
+def make_torch_reflectors(n=100000, nev=2000, nex=600, nrefl=8, width=256, device="cuda",
+                          block=4096, n_lanczos=4, cfg=CFG_HUGE100K, deg=20, tol=1e-10):
+    """H = Q diag(lam) Q^H with Q = R_1 R_2 ... R_nrefl, R_j = I - 2 U_j U_j^H a
+    block reflector (U_j: n x width, orthonormal columns from the QR of a
+    seeded Gaussian), lam i.i.d. U[-1, 1].  H (complex128, n x n, row-major
+    torch tensor) is assembled on the device one block of columns at a
+    time and symmetrised block-pairwise, so no second n x n buffer is needed.
+    Returns dict(H, lam, U (list), V0, S, ...).  ``apply_q(X, U, adjoint)``
+    applies Q or Q^H to a block using the factored form."""
+    import torch
+
+    lam = spectrum_uniform_iid(n, rng(cfg, SLOT_LAMBDA))
+    g = torch.Generator(device=device)
+    g.manual_seed(BASE_SEED + 10 * cfg + SLOT_Q)
+    us = []
+    for _ in range(nrefl):
+        z = torch.randn((n, width), generator=g, dtype=torch.complex128, device=device)
+        u, _r = torch.linalg.qr(z)
+        us.append(u.contiguous())
+        del z, _r
+    lam_t = torch.tensor(lam, dtype=torch.float64, device=device)
+    H = torch.empty((n, n), dtype=torch.complex128, device=device)
+    for j0 in range(0, n, block):
+        j1 = min(n, j0 + block)
+        x = torch.zeros((n, j1 - j0), dtype=torch.complex128, device=device)
+        x[j0:j1, :] = torch.eye(j1 - j0, dtype=torch.complex128, device=device)
+        x = apply_q(x, us, adjoint=True)
+        x *= lam_t[:, None]
+        x = apply_q(x, us, adjoint=False)
+        H[:, j0:j1] = x
+        del x
+    # symmetrise: H <- (H + H^H)/2, block pair by block pair
+    for i0 in range(0, n, block):
+        i1 = min(n, i0 + block)
+        for j0 in range(i0, n, block):
+            j1 = min(n, j0 + block)
+            t = (H[i0:i1, j0:j1] + H[j0:j1, i0:i1].mH) / 2
+            H[i0:i1, j0:j1] = t
+            H[j0:j1, i0:i1] = t.mH
+            del t
+    gv = torch.Generator(device=device)
+    gv.manual_seed(BASE_SEED + 10 * cfg + SLOT_V0)
+    v0 = torch.randn((n, nev + nex), generator=gv, dtype=torch.complex128, device=device)
+    gs = torch.Generator(device=device)
+    gs.manual_seed(BASE_SEED + 10 * cfg + SLOT_S)
+    s = torch.randn((n, n_lanczos), generator=gs, dtype=torch.complex128, device=device)
+    return dict(H=H, lam=lam, U=us, V0=v0, S=s, nev=nev, nex=nex, deg=deg, tol=tol)
+
+
+def apply_q(x, us, adjoint):
+    """Q x (adjoint=False) or Q^H x for Q = R_1 ... R_m, R_j = I - 2 U_j U_j^H."""
+    order = us if adjoint else us[::-1]
+    for u in order:
+        x = x - 2.0 * (u @ (u.mH @ x))
+    return x

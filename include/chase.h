@@ -52,8 +52,8 @@ typedef enum chase_dtype { CHASE_C128 = 0, CHASE_F64 = 1 } chase_dtype;
 
 /* Precision of the filter's matrix products (the rest of the method always
  * runs in FP64).  CHASE_PREC_FP32: complex64/float32 MFMA products with FP32
- * accumulation; a vector switches to FP64 once its residual is below
- * switch_tol (and stays there). */
+ * accumulation; a vector switches to FP64 for good once its residual is
+ * below switch_tol or stops halving between iterations (the FP32 floor). */
 typedef enum chase_prec { CHASE_PREC_FP64 = 0, CHASE_PREC_FP32 = 1 } chase_prec;
 
 typedef struct chase_opts {
@@ -64,7 +64,7 @@ typedef struct chase_opts {
   int lanczos_vecs;    /* number of Lanczos runs, 1..8 (default 4)           */
   int max_iter;        /* subspace iterations before NOCONV (default 50)     */
   int filter_prec;     /* chase_prec (default CHASE_PREC_FP64)                */
-  double switch_tol;   /* low->FP64 switch residual; <=0: 3e-6 for FP32      */
+  double switch_tol;   /* low->FP64 switch residual; <=0: 1e-4 for FP32      */
   int verbose;         /* 1: one line per iteration on stderr                */
   int reserved[7];
 } chase_opts;

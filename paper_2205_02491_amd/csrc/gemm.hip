@@ -22,7 +22,13 @@
 namespace chase {
 namespace {
 
-constexpr int BM = 128, BN = 128, BK = 8;
+constexpr int BM = 128, BN = 128;
+// K chunk per LDS stage: 8 for FP64 operands, 16 for FP32 (same LDS bytes)
+template <typename TC>
+constexpr int bk_of() {
+  return sizeof(TC) == 8 ? 8 : 16;
+}
+constexpr int BK_MIN = 8;
 constexpr int NTHR = 512;
 constexpr int WAVES_M = 2, WAVES_N = 4;
 constexpr int WM = BM / WAVES_M;  // 64 rows per wave
@@ -73,32 +79,55 @@ __device__ constexpr int frag_col(int lk, int r) {
   return sizeof(TC) == 8 ? lk + 4 * r : 4 * lk + r;
 }
 
-// Load element idx (in elements) of a column-major array of memory scalar TM,
-// converting to TC, optionally conjugated.
-template <typename TM, typename TC, bool CPLX>
-__device__ inline Val<TC, CPLX> load_elem(const TM* __restrict__ p, int64_t idx, bool conj) {
-  Val<TC, CPLX> v;
-  if constexpr (CPLX) {
-    if constexpr (sizeof(TM) == 8) {
-      d2v x = *reinterpret_cast<const d2v*>(p + 2 * idx);
-      v.re = (TC)x.x;
-      v.im = conj ? -(TC)x.y : (TC)x.y;
-    } else {
-      f2v x = *reinterpret_cast<const f2v*>(p + 2 * idx);
-      v.re = (TC)x.x;
-      v.im = conj ? -(TC)x.y : (TC)x.y;
-    }
-  } else {
-    v.re = (TC)p[idx];
-  }
-  return v;
+// Raw element as stored in memory (complex: an interleaved pair).  Global
+// loads land in Raw registers and are converted / conjugated only when
+// written to LDS, so no wait on the load is needed before the MFMAs.
+template <typename TM, bool CPLX>
+struct RawT;
+template <>
+struct RawT<double, true> {
+  using type = d2v;
+};
+template <>
+struct RawT<float, true> {
+  using type = f2v;
+};
+template <>
+struct RawT<double, false> {
+  using type = double;
+};
+template <>
+struct RawT<float, false> {
+  using type = float;
+};
+
+template <typename TM, bool CPLX>
+__device__ inline typename RawT<TM, CPLX>::type load_raw(const TM* __restrict__ p, int64_t idx) {
+  using R = typename RawT<TM, CPLX>::type;
+  if constexpr (CPLX)
+    return *reinterpret_cast<const R*>(p + 2 * idx);
+  else
+    return p[idx];
 }
 
-template <typename TC, bool CPLX>
-__device__ inline Val<TC, CPLX> zero_val() {
+template <typename TM, bool CPLX>
+__device__ inline typename RawT<TM, CPLX>::type zero_raw() {
+  using R = typename RawT<TM, CPLX>::type;
+  if constexpr (CPLX)
+    return R{0, 0};
+  else
+    return R(0);
+}
+
+template <typename TC, bool CPLX, typename R>
+__device__ inline Val<TC, CPLX> to_val(R x, bool conj) {
   Val<TC, CPLX> v;
-  v.re = 0;
-  if constexpr (CPLX) v.im = 0;
+  if constexpr (CPLX) {
+    v.re = (TC)x.x;
+    v.im = conj ? -(TC)x.y : (TC)x.y;
+  } else {
+    v.re = (TC)x;
+  }
   return v;
 }
 
@@ -106,6 +135,8 @@ template <typename TA, typename TC, bool CPLX, int OPA, int OPB, int EPI>
 __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int ntiles) {
   using V = Val<TC, CPLX>;
   using acc_t = typename MF<TC>::acc_t;
+  constexpr int BK = bk_of<TC>();
+  constexpr int LOADS = BM * BK / NTHR;  // elements of each operand per thread
   __shared__ V As[2][BK][BM + PAD];
   __shared__ V Bs[2][BK][BN + PAD];
 
@@ -131,10 +162,11 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   const TA* __restrict__ A = static_cast<const TA*>(g.A);
   const double* __restrict__ B = static_cast<const double*>(g.B);
 
-  V ra[2], rb[2];
+  typename RawT<TA, CPLX>::type ra[LOADS];
+  typename RawT<double, CPLX>::type rb[LOADS];
   auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < LOADS; ++e) {
       const int idx = tid + e * NTHR;
       int i, l;
       if constexpr (OPA == OP_N) {
@@ -145,11 +177,9 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
         i = idx / BK;
       }
       const int64_t gi = m0 + i, gk = k0 + l;
-      if (gi < M && gk < kend)
-        ra[e] = load_elem<TA, TC, CPLX>(A, OPA == OP_N ? gi + gk * g.lda : gk + gi * g.lda,
-                                        OPA == OP_C);
-      else
-        ra[e] = zero_val<TC, CPLX>();
+      ra[e] = (gi < M && gk < kend)
+                  ? load_raw<TA, CPLX>(A, OPA == OP_N ? gi + gk * g.lda : gk + gi * g.lda)
+                  : zero_raw<TA, CPLX>();
       int j, lb;
       if constexpr (OPB == OP_N) {
         lb = idx % BK;
@@ -159,16 +189,14 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
         lb = idx / BN;
       }
       const int64_t gj = n0 + j, gkb = k0 + lb;
-      if (gj < N && gkb < kend)
-        rb[e] = load_elem<double, TC, CPLX>(B, OPB == OP_N ? gkb + gj * g.ldb : gj + gkb * g.ldb,
-                                            OPB == OP_C);
-      else
-        rb[e] = zero_val<TC, CPLX>();
+      rb[e] = (gj < N && gkb < kend)
+                  ? load_raw<double, CPLX>(B, OPB == OP_N ? gkb + gj * g.ldb : gj + gkb * g.ldb)
+                  : zero_raw<double, CPLX>();
     }
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
+    for (int e = 0; e < LOADS; ++e) {
       const int idx = tid + e * NTHR;
       int i, l, j, lb;
       if constexpr (OPA == OP_N) {
@@ -185,8 +213,8 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
         j = idx % BN;
         lb = idx / BN;
       }
-      As[buf][l][i] = ra[e];
-      Bs[buf][lb][j] = rb[e];
+      As[buf][l][i] = to_val<TC, CPLX>(ra[e], OPA == OP_C);
+      Bs[buf][lb][j] = to_val<TC, CPLX>(rb[e], OPB == OP_C);
     }
   };
 
@@ -396,11 +424,11 @@ int gemm_row_tiles(int64_t M) { return (int)((M + BM - 1) / BM); }
 void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice) {
   const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
   int64_t s = (1024 + tiles - 1) / tiles;
-  const int64_t smax = (K + 4 * BK - 1) / (4 * BK);  // at least 4 chunks per slice
+  const int64_t smax = (K + 4 * BK_MIN - 1) / (4 * BK_MIN);  // >= 4 chunks per slice
   if (s > smax) s = smax;
   if (s < 1) s = 1;
   int64_t ks = (K + s - 1) / s;
-  ks = (ks + BK - 1) / BK * BK;
+  ks = (ks + BK_MIN - 1) / BK_MIN * BK_MIN;
   s = (K + ks - 1) / ks;
   if (s < 1) s = 1;
   *splits = (int)s;

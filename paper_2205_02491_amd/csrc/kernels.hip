@@ -255,7 +255,46 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
       qs[c][v][1] = CPLX ? q[1] : 0.0;
     }
     __syncthreads();
-    for (int c = 0; c < ncs; ++c) {
+    // 8 columns of H per round: 16 independent 16-byte loads in flight per
+    // thread before the arithmetic that consumes them
+    constexpr int CU = 8;
+    int c = 0;
+    for (; c + CU <= ncs; c += CU) {
+      double hr[CU][LZ_ROWS_PER_THREAD], hi[CU][LZ_ROWS_PER_THREAD];
+#pragma unroll
+      for (int u = 0; u < CU; ++u) {
+        const double* hc = H + (cs + c + u) * ldh * W;
+#pragma unroll
+        for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
+          const int64_t i = r0 + threadIdx.x + r * TPB;
+          hr[u][r] = 0.0;
+          hi[u][r] = 0.0;
+          if (i < n) {
+            if (CPLX) {
+              const d2v h = *reinterpret_cast<const d2v*>(hc + 2 * i);
+              hr[u][r] = h.x;
+              hi[u][r] = h.y;
+            } else {
+              hr[u][r] = hc[i];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < CU; ++u)
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+          if (v < nv) {
+            const double qr = qs[c + u][v][0], qi = qs[c + u][v][1];
+#pragma unroll
+            for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
+              accr[r][v] += hr[u][r] * qr - hi[u][r] * qi;
+              if (CPLX) acci[r][v] += hr[u][r] * qi + hi[u][r] * qr;
+            }
+          }
+        }
+    }
+    for (; c < ncs; ++c) {
       const double* hc = H + (cs + c) * ldh * W;
 #pragma unroll
       for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {

@@ -457,13 +457,18 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   const double norm_est = std::max(std::fabs(bd.mu_1), std::fabs(bd.b_sup));
 
   const bool mixed = o.filter_prec == CHASE_PREC_FP32;
-  const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 3e-6;
+  const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 1e-4;
   if (mixed) to_f32(cplx, H, ldh, h->H32, n, st);
 
   CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
   std::vector<int> m(ne, deg0);
-  std::vector<double> lam(ne, 0.0), res(ne, INFINITY), res_prev(ne, INFINITY);
-  std::vector<char> low(ne, mixed ? 1 : 0);
+  std::vector<double> lam(ne, 0.0), res(ne, INFINITY);
+  // Precision policy (mixed mode).  low[j]: column j is filtered with FP32
+  // products in the coming iteration.  Ritz ranks (absolute position j after
+  // Rayleigh-Ritz) switch to FP64 for good once their residual is below
+  // switch_tol or stops halving between iterations (the FP32 floor).
+  std::vector<char> low(ne, mixed ? 1 : 0), fp64_rank(ne, mixed ? 0 : 1);
+  std::vector<double> res_rank_prev(ne, INFINITY);
   int L = 0;
   bool converged = false;
   std::vector<int> perm(ne);
@@ -500,13 +505,12 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       if (!std::isfinite(r_new[a]) || !std::isfinite(lam[L + a]))
         throw Error(CHASE_ERR_NUMERIC, "non-finite Ritz value or residual");
     }
-    // Ritz vectors come out in ascending order: the per-column history
-    // (precision flag, previous residual) no longer matches column positions,
-    // so it is carried by the smallest-residual rule: a low-precision column
-    // stays low only if it has not reached the switch threshold.
     for (int a = 0; a < ka; ++a) {
-      res_prev[L + a] = res[L + a];
-      res[L + a] = r_new[a];
+      const int j = L + a;
+      res[j] = r_new[a];
+      if (mixed && !fp64_rank[j] && (r_new[a] <= tau_sw || r_new[a] > 0.5 * res_rank_prev[j]))
+        fp64_rank[j] = 1;
+      res_rank_prev[j] = r_new[a];
     }
     // ---- deflation & locking: longest converged prefix
     int nconv = 0;
@@ -515,8 +519,10 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     if (o.verbose) {
       double rmax = 0;
       for (int a = L; a < ne; ++a) rmax = std::max(rmax, res[a]);
-      std::fprintf(stderr, "chase it %d locked %d max_res %.3e mu1 %.6f mune %.6f low %d\n", it + 1,
-                   L, rmax, mu_1, mu_ne, ne - L - n64);
+      std::fprintf(stderr,
+                   "chase it %d: filtered %d (%d fp32), locked %d, max_res %.3e, mu1 %.6f, "
+                   "mune %.6f\n",
+                   it + 1, ka, ka - n64, L, rmax, mu_1, mu_ne);
     }
     if (L >= nev) {
       converged = true;
@@ -532,8 +538,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     for (int a = 0; a < kb; ++a) {
       const int j = L + a;
       m[j] = optimal_degree(res[j], lam[j], c, e, tol, o, deg0);
-      bool lo = mixed && res[j] > tau_sw;
-      grp[a] = lo ? 1 : 0;
+      grp[a] = (mixed && !fp64_rank[j]) ? 1 : 0;
     }
     std::vector<int> idx(kb);
     std::iota(idx.begin(), idx.end(), 0);

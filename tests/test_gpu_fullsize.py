@@ -1,0 +1,72 @@
+"""Full-size checks on the benchmark workload (n=20000 complex128, nev=1000,
+nex=300), in the launch configuration bench.py times:
+- filter: sampled output columns against the oracle's filter of the same
+  columns (the oracle computes them one at a time);
+- solve: properties that hold at any size -- eigenvalues against the planted
+  spectrum, residuals recomputed on the host for sampled pairs, orthonormality.
+"""
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import announce, to_np
+
+pytestmark = pytest.mark.gpu
+
+N, NEV, NEX = 20000, 1000, 300
+
+
+@pytest.fixture(scope="module")
+def problem():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2205_02491_amd as pk
+    pk.lib()
+    announce(f"generating geometric n={N} on the GPU")
+    prob = gen.make_torch("geometric", N, NEV, NEX, device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return pk, prob
+
+
+def test_filter_full_size_sampled_columns(problem):
+    import torch
+    pk, prob = problem
+    announce("full-size filter, 96 columns, sampled against the oracle")
+    H = prob["H"]
+    k = 96
+    X = prob["V0"][:, :k].contiguous()
+    deg = np.repeat(np.array([2, 4, 6], dtype=np.int32), k // 3)
+    b_sup, mu_1, mu_ne = 1.2, -1.0, 0.01
+    Y, mv = pk.chase_filter(H, X, deg, b_sup, mu_1, mu_ne)
+    assert mv == int(deg.sum())
+    Hh = H.cpu().numpy()
+    Yh = to_np(Y)
+    Xh = to_np(X)
+    for a in (0, 31, 32, 63, 64, 95):   # each degree group, first and last column
+        y_ref, _ = oracle.chebyshev_filter(Hh, Xh[:, a:a + 1], deg[a:a + 1], b_sup, mu_1, mu_ne)
+        err = np.max(np.abs(Yh[:, a] - y_ref[:, 0])) / np.max(np.abs(y_ref))
+        assert err < 1e-12, (a, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_full_size_properties(problem, prec):
+    import torch
+    pk, prob = problem
+    announce(f"full-size solve n={N} prec={prec}")
+    opts = pk.default_opts(filter_prec=pk.PREC_FP32 if prec == "fp32" else pk.PREC_FP64)
+    ev, vec, res, st = pk.chase_solve(prob["H"], NEV, NEX, 1e-10, 20, prob["V0"], prob["S"],
+                                      opts=opts)
+    assert st["converged"]
+    lam = prob["lam"]
+    norm = max(abs(lam[0]), abs(lam[-1]))
+    assert np.max(np.abs(ev - lam[:NEV])) <= 2e-10 * norm
+    assert np.all(res <= 1e-10)
+    g = vec.mH @ vec
+    assert float(torch.linalg.matrix_norm(g - torch.eye(NEV, dtype=g.dtype, device=g.device))) < 1e-12
+    Hh = prob["H"].cpu().numpy()
+    vh = to_np(vec)
+    for a in (0, 1, 499, 998, 999):
+        r = Hh @ vh[:, a] - ev[a] * vh[:, a]
+        assert np.linalg.norm(r) <= 1e-10 * max(abs(st["b_sup"]), abs(st["mu_1"]), norm) * 1.01
