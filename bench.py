@@ -178,7 +178,19 @@ def main():
     ap.add_argument("--prec", default="both", choices=["fp64", "fp32", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates the HBM byte "
+                         "counters of rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.calib_copy:
+        import torch
+        x = torch.ones(2**27, dtype=torch.float64, device="cuda")  # 1 GiB
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes": 2**30, "launches": 3}), flush=True)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -275,6 +287,7 @@ def main():
         "converged": r["converged"], "max_resid": r["max_resid"],
         "max_resid_independent": r["max_resid_independent"],
         "max_eig_err_rel": r["max_eig_err_rel"], "phases_s": r["phases"],
+        "qr_shifted_passes": r["qr_shifted"], "qr_householder": r["qr_householder"],
         "roofline": roof,
     }
     if "fp32" in results and main_prec != "fp32":
@@ -282,7 +295,8 @@ def main():
         out["mixed"] = {k: m[k] for k in ("solve_s", "converged", "max_resid", "max_eig_err_rel",
                                           "max_resid_independent",
                                           "iterations", "matvecs_fp64", "matvecs_low",
-                                          "filter_tflops", "phases")}
+                                          "filter_tflops", "phases", "qr_shifted",
+                                          "qr_householder")}
         out["mixed"]["speedup_vs_fp64"] = r["solve_s"] / m["solve_s"]
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

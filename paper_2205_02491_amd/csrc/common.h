@@ -92,6 +92,8 @@ void splitk_reduce(bool cplx, const void* ws, int splits, int64_t M, int64_t N, 
 // flags[0] set to 1 if some S_jj <= 0 or is not finite.
 void gram_scale(bool cplx, void* S, int64_t lds, int64_t k, double shift, double* d,
                 int* flags, hipStream_t st);
+// A(i,i) += shift (real) for a k x k matrix
+void add_diag(bool cplx, void* A, int64_t lda, int64_t k, double shift, hipStream_t st);
 // M = D * triu(Rinv): scale row i by d_i, zero the strictly lower part.
 void triu_rowscale(bool cplx, void* R, int64_t ldr, int64_t k, const double* d,
                    hipStream_t st);

@@ -111,6 +111,13 @@ __global__ void gram_apply_k(double* __restrict__ S, int64_t lds, int64_t k,
   }
 }
 
+template <int W>
+__global__ void add_diag_k(double* __restrict__ A, int64_t lda, int64_t k, double shift) {
+  for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < k;
+       j += (int64_t)gridDim.x * blockDim.x)
+    A[(j + j * lda) * W] += shift;
+}
+
 template <bool CPLX>
 __global__ void triu_rowscale_k(double* __restrict__ R, int64_t ldr, int64_t k,
                                 const double* __restrict__ d) {
@@ -523,6 +530,17 @@ void gram_scale(bool cplx, void* S, int64_t lds, int64_t k, double shift, double
     hipLaunchKernelGGL(gram_apply_k<false>, dim3(nb2), dim3(TPB), 0, st, static_cast<double*>(S),
                        lds, k, d, shift);
   }
+  CHASE_HIP(hipGetLastError());
+}
+
+void add_diag(bool cplx, void* A, int64_t lda, int64_t k, double shift, hipStream_t st) {
+  const int nb = blocks_for(k, TPB, 1024);
+  if (cplx)
+    hipLaunchKernelGGL(add_diag_k<2>, dim3(nb), dim3(TPB), 0, st, static_cast<double*>(A), lda, k,
+                       shift);
+  else
+    hipLaunchKernelGGL(add_diag_k<1>, dim3(nb), dim3(TPB), 0, st, static_cast<double*>(A), lda, k,
+                       shift);
   CHASE_HIP(hipGetLastError());
 }
 

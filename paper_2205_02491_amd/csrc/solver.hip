@@ -254,85 +254,104 @@ void ensure_tape(chase_handle_s* h, int k, int mmax) {
 }
 
 // ------------------------------------------------------------------ QR
-// Orthonormalise X (n x k, ld ldx) keeping its first L columns.  Cholesky QR
-// with column scaling, twice (CholeskyQR2); when the first factor reveals a
-// condition number near 1/sqrt(eps), the first pass is redone with a shift
-// and followed by two plain passes (shifted CholeskyQR3); if even that
-// breaks down, Householder QR.  Scratch: Wb (n x k, ld n), R (k x k).
+// Orthonormalise X (n x k, ld ldx) keeping its first L columns.
+// Cholesky QR with column scaling (S = D X^H X D = R^H R, X <- X D R^{-1})
+// until two consecutive passes are clean (CholeskyQR2).  A pass whose factor
+// shows a condition number near 1/sqrt(eps) (smallest pivot of the scaled
+// factor below 1e-5, or a failed factorisation) is redone on the shifted Gram
+// matrix S + sI, s = 11 (n k + k (k+1)) eps ||XD||_F^2 (shifted Cholesky QR);
+// each shifted pass divides the condition number by about 1/sqrt(s/k), so
+// even numerically rank-deficient filtered blocks are reduced in a few
+// passes.  Householder QR is the last resort.  Scratch: Wb (n x k, ld n),
+// R (k x k), G (k x k, copy of the scaled Gram matrix).
+void householder_qr(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb,
+                    chase_stats* stats, hipStream_t st) {
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  if (stats) stats->qr_householder++;
+  if (L > 0) copy_cols(cplx, X, ldx, Wb, n, n, L, st);
+  if (cplx) {
+    rb_check(rocsolver_zgeqrf(h->rb, n, k, static_cast<rocblas_double_complex*>(X), ldx,
+                              static_cast<rocblas_double_complex*>(h->tau)),
+             "zgeqrf");
+    rb_check(rocsolver_zungqr(h->rb, n, k, k, static_cast<rocblas_double_complex*>(X), ldx,
+                              static_cast<rocblas_double_complex*>(h->tau)),
+             "zungqr");
+  } else {
+    rb_check(rocsolver_dgeqrf(h->rb, n, k, static_cast<double*>(X), ldx,
+                              static_cast<double*>(h->tau)),
+             "dgeqrf");
+    rb_check(rocsolver_dorgqr(h->rb, n, k, k, static_cast<double*>(X), ldx,
+                              static_cast<double*>(h->tau)),
+             "dorgqr");
+  }
+  if (L > 0) copy_cols(cplx, Wb, n, X, ldx, n, L, st);
+  int bad = 0;
+  fill_zero(h->d_flags, sizeof(int), st);
+  check_finite(cplx, X, ldx, n, k, h->d_flags, st);
+  CHASE_HIP(hipMemcpyAsync(&bad, h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipStreamSynchronize(st));
+  if (bad) throw Error(CHASE_ERR_NUMERIC, "QR breakdown (non-finite values)");
+}
+
+void potrf(chase_handle_s* h, void* R, int64_t ldr, int k) {
+  if (h->cplx)
+    rb_check(rocsolver_zpotrf(h->rb, rocblas_fill_upper, k,
+                              static_cast<rocblas_double_complex*>(R), ldr, h->d_info),
+             "zpotrf");
+  else
+    rb_check(rocsolver_dpotrf(h->rb, rocblas_fill_upper, k, static_cast<double*>(R), ldr,
+                              h->d_info),
+             "dpotrf");
+}
+
 void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, chase_stats* stats,
              hipStream_t st) {
   const int64_t n = h->n;
   const bool cplx = h->cplx;
   void* R = h->R;
   const int64_t ldr = k;
-  bool shifted = false;
-  int total = 2;
+  const double u = 1.1102230246251565e-16;
+  const double shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * u * (double)k;
+  constexpr int kMaxShifted = 6;
+  int clean = 0, shifted = 0;
   std::vector<double> diag(k);
   int hinfo[2];
-  for (int pass = 0; pass < total; ++pass) {
-    gram(h, X, ldx, X, ldx, n, k, k, R, ldr, true, st);
-    double shift = 0.0;
-    if (shifted && pass == 0) {
-      const double u = 1.1102230246251565e-16;
-      shift = 11.0 * ((double)n * k + (double)k * (k + 1)) * u * (double)k;
-    }
-    fill_zero(h->d_flags, 2 * sizeof(int), st);
-    gram_scale(cplx, R, ldr, k, shift, h->d_scale, h->d_flags, st);
-    if (cplx)
-      rb_check(rocsolver_zpotrf(h->rb, rocblas_fill_upper, k,
-                                static_cast<rocblas_double_complex*>(R), ldr, h->d_info),
-               "zpotrf");
-    else
-      rb_check(rocsolver_dpotrf(h->rb, rocblas_fill_upper, k, static_cast<double*>(R), ldr,
-                                h->d_info),
-               "dpotrf");
+  auto sync_info = [&](bool want_diag) {
     CHASE_HIP(hipMemcpyAsync(&hinfo[0], h->d_info, sizeof(int), hipMemcpyDeviceToHost, st));
     CHASE_HIP(hipMemcpyAsync(&hinfo[1], h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-    if (pass == 0) {
+    if (want_diag) {
       diag_real(cplx, R, ldr, k, h->d_res, st);
-      CHASE_HIP(hipMemcpyAsync(diag.data(), h->d_res, k * sizeof(double), hipMemcpyDeviceToHost,
-                               st));
+      CHASE_HIP(hipMemcpyAsync(diag.data(), h->d_res, k * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
     }
     CHASE_HIP(hipStreamSynchronize(st));
-    bool ok = hinfo[0] == 0 && hinfo[1] == 0;
-    if (ok && pass == 0) {
-      double dmin = INFINITY;
-      for (double d : diag) dmin = std::min(dmin, std::fabs(d));
-      if (!(dmin >= 1e-6) && !shifted) ok = false;
-    }
+  };
+  while (clean < 2) {
+    gram(h, X, ldx, X, ldx, n, k, k, R, ldr, true, st);
+    fill_zero(h->d_flags, 2 * sizeof(int), st);
+    gram_scale(cplx, R, ldr, k, 0.0, h->d_scale, h->d_flags, st);
+    // keep the scaled Gram matrix in case the pass has to be shifted
+    copy_cols(cplx, R, ldr, h->G, ldr, k, k, st);
+    potrf(h, R, ldr, k);
+    sync_info(true);
+    if (hinfo[1] != 0) return householder_qr(h, X, ldx, k, L, Wb, stats, st);
+    double dmin = INFINITY;
+    for (double d : diag) dmin = std::min(dmin, std::fabs(d));
+    const bool ok = hinfo[0] == 0 && dmin >= 1e-5;
     if (!ok) {
-      if (pass == 0 && !shifted && hinfo[1] == 0) {
-        shifted = true;
-        total = 3;
-        pass = -1;
-        if (stats) stats->qr_shifted++;
-        continue;
-      }
-      // Householder fallback (locked columns restored afterwards)
-      if (stats) stats->qr_householder++;
-      if (L > 0) copy_cols(cplx, X, ldx, Wb, n, n, L, st);
-      if (cplx) {
-        rb_check(rocsolver_zgeqrf(h->rb, n, k, static_cast<rocblas_double_complex*>(X), ldx,
-                                  static_cast<rocblas_double_complex*>(h->tau)),
-                 "zgeqrf");
-        rb_check(rocsolver_zungqr(h->rb, n, k, k, static_cast<rocblas_double_complex*>(X), ldx,
-                                  static_cast<rocblas_double_complex*>(h->tau)),
-                 "zungqr");
-      } else {
-        rb_check(rocsolver_dgeqrf(h->rb, n, k, static_cast<double*>(X), ldx,
-                                  static_cast<double*>(h->tau)),
-                 "dgeqrf");
-        rb_check(rocsolver_dorgqr(h->rb, n, k, k, static_cast<double*>(X), ldx,
-                                  static_cast<double*>(h->tau)),
-                 "dorgqr");
-      }
-      if (L > 0) copy_cols(cplx, Wb, n, X, ldx, n, L, st);
-      fill_zero(h->d_flags, sizeof(int), st);
-      check_finite(cplx, X, ldx, n, k, h->d_flags, st);
-      CHASE_HIP(hipMemcpyAsync(&hinfo[1], h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-      CHASE_HIP(hipStreamSynchronize(st));
-      if (hinfo[1]) throw Error(CHASE_ERR_NUMERIC, "QR breakdown (non-finite values)");
-      return;
+      if (clean > 0 || shifted >= kMaxShifted)
+        return householder_qr(h, X, ldx, k, L, Wb, stats, st);
+      // shifted pass on the saved Gram matrix
+      copy_cols(cplx, h->G, ldr, R, ldr, k, k, st);
+      add_diag(cplx, R, ldr, k, shift, st);
+      potrf(h, R, ldr, k);
+      sync_info(false);
+      if (hinfo[0] != 0) return householder_qr(h, X, ldx, k, L, Wb, stats, st);
+      ++shifted;
+      if (stats) stats->qr_shifted++;
+    } else {
+      ++clean;
     }
     if (cplx)
       rb_check(rocsolver_ztrtri(h->rb, rocblas_fill_upper, rocblas_diagonal_non_unit, k,
