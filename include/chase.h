@@ -52,8 +52,11 @@ typedef enum chase_dtype { CHASE_C128 = 0, CHASE_F64 = 1 } chase_dtype;
 
 /* Precision of the filter's matrix products (the rest of the method always
  * runs in FP64).  CHASE_PREC_FP32: complex64/float32 MFMA products with FP32
- * accumulation; a vector switches to FP64 for good once its residual is
- * below switch_tol or stops halving between iterations (the FP32 floor). */
+ * accumulation; the start block is filtered with the plain recurrence, Ritz
+ * vectors in the defect-correction form (see chase_filter_ritz), whose
+ * rounding error shrinks with the residual; a vector switches to the FP64
+ * filter for good if its residual grows tenfold in an iteration, or once it
+ * is below switch_tol (> 0). */
 typedef enum chase_prec { CHASE_PREC_FP64 = 0, CHASE_PREC_FP32 = 1 } chase_prec;
 
 typedef struct chase_opts {
@@ -64,7 +67,7 @@ typedef struct chase_opts {
   int lanczos_vecs;    /* number of Lanczos runs, 1..8 (default 4)           */
   int max_iter;        /* subspace iterations before NOCONV (default 50)     */
   int filter_prec;     /* chase_prec (default CHASE_PREC_FP64)                */
-  double switch_tol;   /* low->FP64 switch residual; <=0: 1e-4 for FP32      */
+  double switch_tol;   /* FP32->FP64 switch residual; <= 0: never           */
   int verbose;         /* 1: one line per iteration on stderr                */
   int reserved[7];
 } chase_opts;
@@ -138,6 +141,22 @@ chase_status chase_filter(chase_handle_t handle, const void* H_dev, int64_t ldh,
                           void* X_dev, int64_t ldx, int k, const int* degrees_host,
                           double b_sup, double mu_1, double mu_ne, int prec,
                           int record_tape, int64_t* matvecs, void* stream);
+
+/* The same filter applied to Ritz vectors in defect-correction form:
+ * V_dev (n x k, ld ldv, in/out) holds Ritz vectors v_a with Ritz values
+ * theta_host[a] and R_dev (n x k, ld ldr) their residuals r_a = H v_a -
+ * theta_a v_a.  Since (H - gamma I) v = (theta - gamma) v + r, p(H) v =
+ * T_m(theta) v + D_m where D follows the three-term recurrence of Eq. (3)
+ * started from D_0 = 0 with the extra term alpha_s T_{s-1}(theta) r_a; only
+ * D is multiplied by H, so with prec = CHASE_PREC_FP32 the rounding error is
+ * relative to ||r|| rather than ||p(H) v||.  Degrees as in chase_filter.
+ * matvecs (may be NULL) receives the number of column products (m_a - 1 per
+ * column: the first step needs none). */
+chase_status chase_filter_ritz(chase_handle_t handle, const void* H_dev, int64_t ldh,
+                               void* V_dev, int64_t ldv, const void* R_dev, int64_t ldr,
+                               const double* theta_host, int k, const int* degrees_host,
+                               double b_sup, double mu_1, double mu_ne, int prec,
+                               int64_t* matvecs, void* stream);
 
 /* QR step of Algorithm 1: orthonormalise the n x k block X_dev (ld ldx)
  * in place, keeping its first `locked` columns (assumed orthonormal)

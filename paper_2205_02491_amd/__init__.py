@@ -27,7 +27,7 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
            4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}
 
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
-            "chase_solve", "chase_lanczos", "chase_filter", "chase_qr",
+            "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
             "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_filter_adjoint",
             "chase_last_error"]
 
@@ -90,6 +90,9 @@ def lib():
     L.chase_lanczos.restype = ci
     L.chase_filter.argtypes = [vp, vp, i64, vp, i64, ci, pi, cd, cd, cd, ci, ci, pi64, vp]
     L.chase_filter.restype = ci
+    L.chase_filter_ritz.argtypes = [vp, vp, i64, vp, i64, vp, i64, pd, ci, pi, cd, cd, cd, ci,
+                                    pi64, vp]
+    L.chase_filter_ritz.restype = ci
     L.chase_qr.argtypes = [vp, vp, i64, ci, ci, vp]
     L.chase_qr.restype = ci
     L.chase_rayleigh_ritz.argtypes = [vp, vp, i64, vp, i64, ci, cd, pd, pd, vp]
@@ -276,6 +279,26 @@ def chase_filter(H, X, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64, record_tape=
     return buf.mH, mv.value
 
 
+def chase_filter_ritz(H, V, R, theta, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64,
+                      handle=None):
+    """p(H) V in the defect-correction form for vectors V (n x k) with shifts
+    theta (k) and residuals R = H V - V diag(theta).  Returns (Y, matvecs)."""
+    n, k = V.shape
+    if handle is None:
+        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1, H.dtype)
+    vbuf = _colmajor(V.to(H.dtype))
+    rbuf = _colmajor(R.to(H.dtype))
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    mv = ctypes.c_int64()
+    _check(lib().chase_filter_ritz(handle.ptr, _dev(H), n, _dev(vbuf), n, _dev(rbuf), n,
+                                   th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k,
+                                   deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                   float(b_sup), float(mu_1), float(mu_ne), int(prec),
+                                   ctypes.byref(mv), _stream()))
+    return vbuf.mH, mv.value
+
+
 def chase_qr(X, locked=0, handle=None):
     """Orthonormalise X (n x k) keeping its first `locked` columns."""
     n, k = X.shape
@@ -329,6 +352,7 @@ def chase_filter_adjoint(H, gY, dH, handle, want_gX=False):
 from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
-           "chase_solve", "chase_lanczos", "chase_filter", "chase_qr", "chase_rayleigh_ritz",
+           "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
+           "chase_rayleigh_ritz",
            "chase_eigval_adjoint", "chase_filter_adjoint", "ChaseEigh", "chase_eigh",
            "filtered_block", "lib", "EXPORTED"]

@@ -69,6 +69,11 @@ struct GemmArgs {
   int splits;            // SPLITK: number of K slices (grid z)
   int64_t kslice;        // SPLITK: K length per slice (multiple of the K tile)
   int a_f32;             // A stored as c64/float (mixed-precision copy of H)
+  // CHEB: optional forcing term + colcoef[j] * F(i, j) (defect-correction
+  // form of the filter); RESID: optional store of the residual block to F
+  const double* colcoef;
+  void* F;
+  int64_t ldf;
 };
 
 // Launch the tile GEMM. cplx selects complex (c128) vs real (double) data.
@@ -105,6 +110,9 @@ void resid_finish(const double* partial, int tiles, int64_t N, double inv_scale,
 // V = V * diag(g) (columns scaled by real g)
 void scale_cols(bool cplx, void* V, int64_t ldv, int64_t n, int64_t k, const double* g,
                 hipStream_t st);
+// Y[:, j] = (a ? a[j] : 1) X[:, j] + (b ? b[j] : 0) Y[:, j]   (a, b on the device)
+void axpby_cols(bool cplx, const double* a, const void* X, int64_t ldx, const double* b, void* Y,
+                int64_t ldy, int64_t n, int64_t k, hipStream_t st);
 // Y += a * X for n x k blocks
 void axpy_cols(bool cplx, double a, const void* X, int64_t ldx, void* Y, int64_t ldy, int64_t n,
                int64_t k, hipStream_t st);

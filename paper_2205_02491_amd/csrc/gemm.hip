@@ -2,6 +2,7 @@
 // epilogues the ChASE hot path needs fused in:
 //   - the Chebyshev step of Eq. (3): out = alpha*(H X_s - gamma X_s) + beta X_{s-2}
 //     (the shift of H by gamma is applied to the product, so H stays const),
+//     optionally + c_j F_j (the forcing term of the filter's defect form),
 //   - split-K partial sums for the tall-skinny Gram / projection products of
 //     the QR and Rayleigh-Ritz steps,
 //   - per-column residual norms ||H v - lambda v||^2 of the residual step.
@@ -318,9 +319,13 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
               const double xr = (double)acc_re[fm][fn][r] - lam * v.x;
               const double xi = (double)acc_im[fm][fn][r] - lam * v.y;
               colsum[fn][r] += xr * xr + xi * xi;
+              if (g.F)
+                *reinterpret_cast<d2v*>(static_cast<double*>(g.F) + 2 * (i + j * g.ldf)) =
+                    d2v{xr, xi};
             } else {
               const double xr = (double)acc_re[fm][fn][r] - lam * Vd[i + j * g.ldv];
               colsum[fn][r] += xr * xr;
+              if (g.F) static_cast<double*>(g.F)[i + j * g.ldf] = xr;
             }
           }
         }
@@ -391,6 +396,19 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
               vi += g.beta * y.y;
             } else {
               vr += g.beta * Cd[o];
+            }
+          }
+          if constexpr (EPI == EPI_CHEB) {
+            if (g.colcoef) {
+              const double cj = g.colcoef[j];
+              const double* Fd = static_cast<const double*>(g.F);
+              if constexpr (CPLX) {
+                const d2v f = *reinterpret_cast<const d2v*>(Fd + 2 * (i + j * g.ldf));
+                vr += cj * f.x;
+                vi += cj * f.y;
+              } else {
+                vr += cj * Fd[i + j * g.ldf];
+              }
             }
           }
           if constexpr (CPLX) {

@@ -169,6 +169,27 @@ __global__ void scale_cols_k(double* __restrict__ V, int64_t ldv, int64_t n, int
 }
 
 template <int W>
+__global__ void axpby_cols_k(const double* __restrict__ a, const double* __restrict__ X, int64_t ldx,
+                             const double* __restrict__ b, double* __restrict__ Y, int64_t ldy,
+                             int64_t n, int64_t k) {
+  for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
+    const double aj = a ? a[j] : 1.0;
+    const double* x = X + j * ldx * W;
+    double* y = Y + j * ldy * W;
+    if (b) {
+      const double bj = b[j];
+      for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * W;
+           i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = aj * x[i] + bj * y[i];
+    } else {
+      for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n * W;
+           i += (int64_t)gridDim.x * blockDim.x)
+        y[i] = aj * x[i];
+    }
+  }
+}
+
+template <int W>
 __global__ void axpy_cols_k(double a, const double* __restrict__ X, int64_t ldx,
                             double* __restrict__ Y, int64_t ldy, int64_t n, int64_t k) {
   for (int64_t j = blockIdx.y; j < k; j += gridDim.y) {
@@ -583,6 +604,19 @@ void scale_cols(bool cplx, void* V, int64_t ldv, int64_t n, int64_t k, const dou
   else
     hipLaunchKernelGGL(scale_cols_k<false>, grid, dim3(TPB), 0, st, static_cast<double*>(V), ldv,
                        n, k, g);
+  CHASE_HIP(hipGetLastError());
+}
+
+void axpby_cols(bool cplx, const double* a, const void* X, int64_t ldx, const double* b, void* Y,
+                int64_t ldy, int64_t n, int64_t k, hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  dim3 grid(blocks_for(n * (cplx ? 2 : 1), TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
+  if (cplx)
+    hipLaunchKernelGGL(axpby_cols_k<2>, grid, dim3(TPB), 0, st, a, static_cast<const double*>(X),
+                       ldx, b, static_cast<double*>(Y), ldy, n, k);
+  else
+    hipLaunchKernelGGL(axpby_cols_k<1>, grid, dim3(TPB), 0, st, a, static_cast<const double*>(X),
+                       ldx, b, static_cast<double*>(Y), ldy, n, k);
   CHASE_HIP(hipGetLastError());
 }
 

@@ -41,7 +41,9 @@ struct chase_handle_s {
   int *d_flags = nullptr, *d_info = nullptr, *d_perm = nullptr;
   void* tau = nullptr;
   LanczosBufs lz{};
-  void* H32 = nullptr;  // low-precision copy of H for the FP32 filter
+  void* H32 = nullptr;   // low-precision copy of H for the FP32 filter
+  void* Rres = nullptr;  // residual vectors H v - theta v of the active block (FP32 mode)
+  double* d_coef = nullptr;  // per-step, per-column coefficients of the filter's defect form
   // filter tape (record_tape)
   void* tape = nullptr;
   size_t tape_bytes = 0;
@@ -77,6 +79,13 @@ void* dev_alloc(chase_handle_s* h, size_t bytes) {
   return p;
 }
 
+// Host-to-device copy of a small pageable host array; returns once the copy
+// has completed so the host array may go out of scope.
+void h2d_sync(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  CHASE_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+  CHASE_HIP(hipStreamSynchronize(st));
+}
+
 void rb_check(rocblas_status s, const char* what) {
   if (s != rocblas_status_success)
     throw Error(CHASE_ERR_HIP, std::string(what) + " failed: " + rocblas_status_to_string(s));
@@ -94,6 +103,8 @@ size_t splitk_ws_elems(int ne) {
   return mx;
 }
 
+constexpr int kMaxDegree = 1000;  // largest filter degree any entry point accepts
+
 struct Sizes {
   size_t blocks, small, lz, ws, h32, total;
   int lz_splits;
@@ -109,13 +120,14 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
   s.small = (size_t)ne * 8 * 5 + (size_t)gemm_row_tiles(n) * ne * 8 + 64 + (size_t)ne * 4 +
             (size_t)ne * esz;
   s.lz = lanczos_bytes(cplx, n, o.lanczos_vecs, o.lanczos_steps, &s.lz_splits);
-  s.h32 = o.filter_prec == CHASE_PREC_FP32 ? (size_t)n * n * esz / 2 : 0;
+  s.h32 = o.filter_prec == CHASE_PREC_FP32 ? (size_t)n * n * esz / 2 + (size_t)n * ne * esz : 0;
+  s.small += (size_t)(kMaxDegree + 1) * ne * 8;
   s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
   return s;
 }
 
 void validate_opts(const chase_opts& o) {
-  CHASE_REQUIRE(o.max_deg >= 2 && o.max_deg <= 1000, "max_deg out of range [2,1000]");
+  CHASE_REQUIRE(o.max_deg >= 2 && o.max_deg <= kMaxDegree, "max_deg out of range [2,1000]");
   CHASE_REQUIRE(o.deg_extra >= 0, "deg_extra < 0");
   CHASE_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 200, "lanczos_steps out of range");
   CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
@@ -231,6 +243,87 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     h->tape_coef = cf;
     h->tape_k = k;
     h->tape_valid = true;
+  }
+}
+
+// Defect-correction form of the filter for Ritz vectors.  V (n x k, ld ldv)
+// holds Ritz vectors v_a with Ritz values theta[a] and residuals
+// R (n x k, ld ldr), r_a = H v_a - theta_a v_a.  With T_s the scaled
+// Chebyshev polynomials of Eq. (3) (T_0 = 1):
+//   p(H) v = T_m(theta) v + D_m,   D_0 = 0,  D_1 = alpha_1 r,
+//   D_s = alpha_s (H - gamma I) D_{s-1} + beta_s D_{s-2} + alpha_s T_{s-1}(theta) r,
+// which follows from (H - gamma I) v = (theta - gamma) v + r.  The rounding
+// error of the products H D is relative to ||D|| ~ ||r|| instead of ||p(H) v||,
+// so FP32 products keep the convergence of the FP64 filter down to FP64
+// residual levels.  D ping-pongs between W1 (odd s) and W2 (even s), ld n.
+void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, int64_t ldv,
+                       const void* R, int64_t ldr, void* W1, void* W2, int k, const int* deg,
+                       const double* theta, double b_sup, double mu_1, double mu_ne, Prec prec,
+                       FilterTiming& ft, hipStream_t st) {
+  if (k <= 0) return;
+  const int64_t n = h->n;
+  const int mmax = deg[k - 1];
+  const std::vector<Coef> cf = cheb_coefficients(mmax, b_sup, mu_1, mu_ne);
+  // coefficient table: row s (1..mmax) = alpha_s T_{s-1}(theta_a); row 0 = T_{m_a}(theta_a)
+  std::vector<double> tab((size_t)(mmax + 1) * k, 0.0);
+  for (int a = 0; a < k; ++a) {
+    double tp = 0.0, tc = 1.0;
+    for (int s = 1; s <= deg[a]; ++s) {
+      const Coef& c = cf[s - 1];
+      tab[(size_t)s * k + a] = c.alpha * tc;
+      const double tn = c.alpha * (theta[a] - c.gamma) * tc + c.beta * tp;
+      tp = tc;
+      tc = tn;
+    }
+    tab[a] = tc;
+  }
+  h2d_sync(h->d_coef, tab.data(), tab.size() * 8, st);
+  const void* Ah = H;
+  int64_t lda = ldh;
+  int a_f32 = 0;
+  if (prec == PREC_F32 && h->H32) {
+    Ah = h->H32;
+    lda = n;
+    a_f32 = 1;
+  }
+  while (h->evs.size() < 2 * (size_t)mmax) {
+    hipEvent_t e;
+    CHASE_HIP(hipEventCreate(&e));
+    h->evs.push_back(e);
+  }
+  // D_1 = alpha_1 r ; D_0 = 0
+  axpby_cols(h->cplx, h->d_coef + k, R, ldr, nullptr, W1, n, n, k, st);
+  fill_zero(W2, (int64_t)n * k * (int64_t)h->esz, st);
+  for (int s = 2; s <= mmax; ++s) {
+    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    const int cols = k - a0;
+    if (cols <= 0) continue;
+    void* src = (s & 1) ? W2 : W1;  // D_{s-1}
+    void* dst = (s & 1) ? W1 : W2;  // D_s over D_{s-2}
+    GemmArgs g = gargs(n, cols, n, Ah, lda, off(src, (int64_t)a0 * n, h->esz), n,
+                       off(dst, (int64_t)a0 * n, h->esz), n);
+    g.alpha = cf[s - 1].alpha;
+    g.gamma = cf[s - 1].gamma;
+    g.beta = cf[s - 1].beta;
+    g.a_f32 = a_f32;
+    g.colcoef = h->d_coef + (size_t)s * k + a0;
+    g.F = const_cast<char*>(static_cast<const char*>(R)) + (int64_t)a0 * ldr * (int64_t)h->esz;
+    g.ldf = ldr;
+    CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
+    gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
+    CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
+    ft.matvecs += cols;
+    ft.launches += 1;
+  }
+  // p(H) v = T_m(theta) v + D_m  (degrees are even: D_m is in W2)
+  axpby_cols(h->cplx, nullptr, W2, n, h->d_coef, V, ldv, n, k, st);
+  CHASE_HIP(hipStreamSynchronize(st));
+  for (int s = 2; s <= mmax; ++s) {
+    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    if (k - a0 <= 0) continue;
+    float ms = 0.f;
+    CHASE_HIP(hipEventElapsedTime(&ms, h->evs[2 * (s - 1)], h->evs[2 * (s - 1) + 1]));
+    ft.ktime += ms * 1e-3;
   }
 }
 
@@ -373,7 +466,7 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
 // (h->d_evals, h->d_res).  Scratch: P (n x k, ld n), Zb (n x k, ld n).
 void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq, int k,
              double norm_scale, void* P, void* Zb, double* t_rr, double* t_resid,
-             hipStream_t st) {
+             hipStream_t st, void* Rout = nullptr, int64_t ldr = 0) {
   const int64_t n = h->n;
   const bool cplx = h->cplx;
   auto t0 = clk::now();
@@ -400,6 +493,8 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
   g.V = Zb;
   g.ldv = n;
   g.partial = h->d_partial;
+  g.F = Rout;
+  g.ldf = ldr;
   gemm(cplx, PREC_F64, OP_N, OP_N, EPI_RESID, g, st);
   resid_finish(h->d_partial, gemm_row_tiles(n), k, 1.0 / norm_scale, h->d_res, st);
   copy_cols(cplx, Zb, n, Q, ldq, n, k, st);
@@ -476,16 +571,19 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   const double norm_est = std::max(std::fabs(bd.mu_1), std::fabs(bd.b_sup));
 
   const bool mixed = o.filter_prec == CHASE_PREC_FP32;
-  const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 1e-4;
+  const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
   if (mixed) to_f32(cplx, H, ldh, h->H32, n, st);
 
   CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
   std::vector<int> m(ne, deg0);
   std::vector<double> lam(ne, 0.0), res(ne, INFINITY);
   // Precision policy (mixed mode).  low[j]: column j is filtered with FP32
-  // products in the coming iteration.  Ritz ranks (absolute position j after
-  // Rayleigh-Ritz) switch to FP64 for good once their residual is below
-  // switch_tol or stops halving between iterations (the FP32 floor).
+  // products in the coming iteration: the start block with the plain
+  // recurrence, Ritz vectors with the defect-correction form (whose FP32
+  // rounding error scales with the residual, so it converges as the FP64
+  // filter does).  A Ritz rank (absolute position j after Rayleigh-Ritz)
+  // switches to the FP64 filter for good if its residual grows tenfold in an
+  // iteration, or once it is below switch_tol when that option is set.
   std::vector<char> low(ne, mixed ? 1 : 0), fp64_rank(ne, mixed ? 0 : 1);
   std::vector<double> res_rank_prev(ne, INFINITY);
   int L = 0;
@@ -502,9 +600,15 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     if (n64 > 0)
       run_filter(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n64, &m[L], b_sup,
                  mu_1, mu_ne, PREC_F64, false, ft64, st);
-    if (ka - n64 > 0)
-      run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
-                 &m[L + n64], b_sup, mu_1, mu_ne, PREC_F32, false, ftlo, st);
+    if (ka - n64 > 0) {
+      if (it == 0)  // start block: no Ritz pairs yet, plain FP32 products
+        run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
+                   &m[L + n64], b_sup, mu_1, mu_ne, PREC_F32, false, ftlo, st);
+      else  // Ritz vectors: defect-correction form with FP32 products
+        run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
+                          off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z, ka - n64,
+                          &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, PREC_F32, ftlo, st);
+    }
     auto F1 = clk::now();
     stats.t_filter += secs(F0, F1);
     // ---- QR of [Y V]
@@ -513,7 +617,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     stats.t_qr += secs(F1, Q1);
     // ---- Rayleigh-Ritz + residuals on the active part
     rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
-            &stats.t_resid, st);
+            &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n);
     check_info(h, st, "Hermitian eigensolver");
     CHASE_HIP(hipMemcpyAsync(&lam[L], h->d_evals, ka * sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<double> r_new(ka);
@@ -527,7 +631,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     for (int a = 0; a < ka; ++a) {
       const int j = L + a;
       res[j] = r_new[a];
-      if (mixed && !fp64_rank[j] && (r_new[a] <= tau_sw || r_new[a] > 0.5 * res_rank_prev[j]))
+      if (mixed && !fp64_rank[j] && (r_new[a] <= tau_sw || r_new[a] > 10.0 * res_rank_prev[j]))
         fp64_rank[j] = 1;
       res_rank_prev[j] = r_new[a];
     }
@@ -580,9 +684,13 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       res[L + a] = res2[a];
       low[L + a] = low2[a];
     }
-    CHASE_HIP(hipMemcpyAsync(h->d_perm, idx.data(), kb * sizeof(int), hipMemcpyHostToDevice, st));
+    h2d_sync(h->d_perm, idx.data(), kb * sizeof(int), st);
     gather_cols(cplx, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n, kb, h->d_perm, st);
     copy_cols(cplx, h->W, n, off(h->V, (int64_t)L * n, h->esz), n, n, kb, st);
+    if (mixed) {
+      gather_cols(cplx, off(h->Rres, (int64_t)L * n, h->esz), n, h->W, n, n, kb, h->d_perm, st);
+      copy_cols(cplx, h->W, n, off(h->Rres, (int64_t)L * n, h->esz), n, n, kb, st);
+    }
   }
   // ---- output: lowest nev of the locked pairs (or of all pairs on NOCONV)
   const int pool = converged ? L : ne;
@@ -594,7 +702,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     evals[i] = lam[idx[i]];
     if (resid) resid[i] = res[idx[i]];
   }
-  CHASE_HIP(hipMemcpyAsync(h->d_perm, idx.data(), nev * sizeof(int), hipMemcpyHostToDevice, st));
+  h2d_sync(h->d_perm, idx.data(), nev * sizeof(int), st);
   gather_cols(cplx, h->V, n, evecs, ldv, n, nev, h->d_perm, st);
   CHASE_HIP(hipStreamSynchronize(st));
   stats.locked = L;
@@ -701,7 +809,11 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     h->lz.nrmp = static_cast<double*>(dev_alloc(h, 128 * nv * 8));
     h->lz.alpha = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
     h->lz.beta = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
-    if (o.filter_prec == CHASE_PREC_FP32) h->H32 = dev_alloc(h, (size_t)n * n * h->esz / 2);
+    if (o.filter_prec == CHASE_PREC_FP32) {
+      h->H32 = dev_alloc(h, (size_t)n * n * h->esz / 2);
+      h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
+    }
+    h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
     rb_check(rocblas_create_handle(&h->rb), "rocblas_create_handle");
     *out = h;
   });
@@ -783,7 +895,7 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
                       mu_1 < mu_ne && mu_ne < b_sup,
                   "need mu_1 < mu_ne < b_sup");
     for (int a = 0; a < k; ++a) {
-      CHASE_REQUIRE(degrees[a] >= 2 && degrees[a] % 2 == 0 && degrees[a] <= 1000,
+      CHASE_REQUIRE(degrees[a] >= 2 && degrees[a] % 2 == 0 && degrees[a] <= kMaxDegree,
                     "degrees must be even and in [2, 1000]");
       CHASE_REQUIRE(a == 0 || degrees[a] >= degrees[a - 1], "degrees must be non-decreasing");
     }
@@ -795,6 +907,35 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     h->tape_valid = false;
     run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne,
                prec == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64, record_tape != 0, ft, st);
+    if (matvecs) *matvecs = ft.matvecs;
+  });
+}
+
+chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, void* V,
+                               int64_t ldv, const void* R, int64_t ldr, const double* theta, int k,
+                               const int* degrees, double b_sup, double mu_1, double mu_ne,
+                               int prec, int64_t* matvecs, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && V && R && theta && degrees, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n && ldv >= h->n && ldr >= h->n, "leading dimension smaller than n");
+    CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32, "unknown precision");
+    CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
+                      mu_1 < mu_ne && mu_ne < b_sup,
+                  "need mu_1 < mu_ne < b_sup");
+    for (int a = 0; a < k; ++a) {
+      CHASE_REQUIRE(std::isfinite(theta[a]), "theta must be finite");
+      CHASE_REQUIRE(degrees[a] >= 2 && degrees[a] % 2 == 0 && degrees[a] <= kMaxDegree,
+                    "degrees must be even and in [2, 1000]");
+      CHASE_REQUIRE(a == 0 || degrees[a] >= degrees[a - 1], "degrees must be non-decreasing");
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
+    FilterTiming ft;
+    run_filter_defect(h, H, ldh, V, ldv, R, ldr, h->W, h->Z, k, degrees, theta, b_sup, mu_1,
+                      mu_ne, prec == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64, ft, st);
     if (matvecs) *matvecs = ft.matvecs;
   });
 }
@@ -843,7 +984,7 @@ chase_status chase_eigval_adjoint(chase_handle_t h, const void* V, int64_t ldv, 
     const int64_t n = h->n;
     // Z = V diag(g); dH += Z V^H
     copy_cols(h->cplx, V, ldv, h->Z, n, n, m, st);
-    CHASE_HIP(hipMemcpyAsync(h->d_g, g_host, m * 8, hipMemcpyHostToDevice, st));
+    h2d_sync(h->d_g, g_host, m * 8, st);
     scale_cols(h->cplx, h->Z, n, n, m, h->d_g, st);
     GemmArgs g = gargs(n, n, m, h->Z, n, V, ldv, dH, ldd);
     g.beta = 1.0;

@@ -74,6 +74,50 @@ def test_filter_fp32_error_bound(pk):
     assert 1e-9 < err < 5e-5, err
 
 
+@pytest.mark.parametrize("cplx", [True, False])
+def test_filter_ritz_defect_form_matches_oracle(pk, cplx):
+    """The defect-correction form computes exactly p(H) v for any vector v and
+    shift theta with r = H v - theta v (here: random v, random theta)."""
+    announce(f"filter_ritz FP64 parity cplx={cplx}")
+    n, k = 650, 70
+    h, lam, q, g = _problem(n, cplx, 2200 + cplx)
+    v = gen.gaussian(g, (n, k), cplx)
+    theta = g.uniform(-1, 1, size=k)
+    r = h @ v - v * theta[None, :]
+    deg = np.sort(2 * g.integers(1, 12, size=k)).astype(np.int32)
+    b_sup, mu_1, mu_ne = 1.04, -1.0, -0.5
+    y_ref, mv_ref = oracle.chebyshev_filter(h, v, deg, b_sup, mu_1, mu_ne)
+    y, mv = pk.chase_filter_ritz(to_gpu(h), to_gpu(v), to_gpu(r), theta, deg, b_sup, mu_1, mu_ne)
+    assert mv == mv_ref - k          # the first step needs no product
+    y = to_np(y)
+    for a in range(k):
+        err = np.max(np.abs(y[:, a] - y_ref[:, a])) / np.max(np.abs(y_ref[:, a]))
+        assert err < 1e-11, (a, deg[a], err)
+
+
+def test_filter_ritz_fp32_error_scales_with_residual(pk):
+    """FP32 products: the plain filter's error is ~u_32 relative to the output,
+    the defect form's is ~u_32 relative to the residual; for Ritz-like vectors
+    with residual ~1e-6 the latter must be orders of magnitude smaller."""
+    announce("filter_ritz FP32 error vs plain FP32")
+    n, k = 900, 40
+    h, lam, q, g = _problem(n, True, 2300)
+    v = q[:, :k] + 1e-6 * gen.gaussian(g, (n, k), True)
+    v /= np.linalg.norm(v, axis=0)[None, :]
+    theta = np.real(np.sum(v.conj() * (h @ v), axis=0))
+    r = h @ v - v * theta[None, :]
+    deg = np.full(k, 20, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 1.02, -1.0, lam[60]
+    y_ref, _ = oracle.chebyshev_filter(h, v, deg, b_sup, mu_1, mu_ne)
+    y_d, _ = pk.chase_filter_ritz(to_gpu(h), to_gpu(v), to_gpu(r), theta, deg, b_sup, mu_1,
+                                  mu_ne, prec=pk.PREC_FP32)
+    y_p, _ = pk.chase_filter(to_gpu(h), to_gpu(v), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_FP32)
+    e_d = rel_err(to_np(y_d), y_ref)
+    e_p = rel_err(to_np(y_p), y_ref)
+    assert e_p > 1e-8
+    assert e_d < 1e-11 and e_d < 1e-3 * e_p, (e_d, e_p)
+
+
 # ------------------------------------------------------------------ Lanczos
 @pytest.mark.parametrize("cplx", [True, False])
 def test_lanczos_matches_oracle(pk, cplx):
