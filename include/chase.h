@@ -101,13 +101,16 @@ size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex,
 /* Create a handle on the current HIP device and allocate its workspace
  * once (as the paper pre-allocates its library buffers, Section 2.3).
  * Requires 1 <= nev, 1 <= nex, nev+nex <= n.  opts may be NULL (defaults).
- * CHASE_ERR_NOMEM if the workspace exceeds the free device memory. */
+ * CHASE_ERR_NOMEM if the workspace exceeds the free device memory.  With
+ * CHASE_PREC_FP32 the workspace includes a complex64 copy of H when it fits
+ * (chase_workspace_bytes counts it); otherwise H is rounded on the fly. */
 chase_status chase_create(chase_handle_t* handle, chase_dtype dtype, int64_t n,
                           int nev, int nex, const chase_opts* opts);
 void chase_destroy(chase_handle_t handle);
 
-/* Algorithm 1.  Inputs: H_dev (n x n, ld ldh), tol > 0 (residual bound
- * relative to max(|mu_1|,|b_sup|) of the Lanczos bounds), degree >= 2
+/* Algorithm 1.  Inputs: H_dev (n x n, ld ldh), tol > 0 (bound on
+ * ||H v - lambda v||_2 relative to the largest Lanczos Ritz value in
+ * magnitude, a lower bound of ||H||_2), degree >= 2
  * (initial degree, rounded up to even), V0_dev (n x (nev+nex), ld n: the
  * start block), S_dev (n x lanczos_vecs, ld n: Lanczos start vectors).
  * Outputs: evals_host[nev] ascending, evecs_dev (n x nev, ld ldv),

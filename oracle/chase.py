@@ -136,6 +136,17 @@ def spectral_bounds(H, S, steps, n_e, reorth=False):
     return float(b_sup), float(mu_1), float(mu_ne), runs
 
 
+def lanczos_norm(runs):
+    """Largest Ritz value in magnitude over the Lanczos runs: Ritz values lie
+    in [lambda_min, lambda_max], so this is a lower bound of ||H||_2 (the
+    residual normalisation of the solver)."""
+    best = 0.0
+    for a, b in runs:
+        th, _ = tridiag_eig(a, b)
+        best = max(best, abs(th[0]), abs(th[-1]))
+    return float(best)
+
+
 # ---------------------------------------------------------------- filter
 def filter_coefficients(m, b_sup, mu_1, mu_ne):
     """Scalars (alpha_s, gamma_s, beta_s) of Eq. (3) for steps s = 1..m of the
@@ -223,8 +234,8 @@ def rayleigh_ritz(H, Qa):
 
 def residual_norms(H, V, theta, norm_est):
     """Residual step: ||H v_a - theta_a v_a||_2 / norm_est per column, with
-    norm_est = max(|mu_1|, |b_sup|) from the Lanczos bounds (reading of the
-    relative tolerance)."""
+    norm_est the largest Lanczos Ritz value in magnitude (a lower bound of
+    ||H||_2, so res <= tol guarantees ||H v - theta v|| <= tol ||H||_2)."""
     r = H @ V - V * theta[None, :]
     return np.linalg.norm(r, axis=0) / norm_est
 
@@ -265,17 +276,17 @@ def solve(H, nev, nex, tol, deg, V0, S, opts: Options | None = None):
 
     Readings: locking takes the longest converged prefix in ascending Ritz
     order; the bound update uses mu_1 = min and mu_ne = max of the locked and
-    current Ritz values with b_sup fixed; residuals are relative to
-    max(|mu_1|, |b_sup|) of the Lanczos bounds; degrees are even.
+    current Ritz values with b_sup fixed; residuals are relative to the
+    largest Lanczos Ritz value in magnitude; degrees are even.
     Returns (evals[nev], evecs[n, nev], resid[nev], Stats)."""
     opts = opts or Options()
     n = H.shape[0]
     n_e = nev + nex
     deg = deg + deg % 2
     st = Stats()
-    b_sup, mu_1, mu_ne, _ = spectral_bounds(H, S, opts.lanczos_steps, n_e)
+    b_sup, mu_1, mu_ne, runs = spectral_bounds(H, S, opts.lanczos_steps, n_e)
     st.b_sup, st.mu_1, st.mu_ne = b_sup, mu_1, mu_ne
-    norm_est = max(abs(mu_1), abs(b_sup))
+    norm_est = lanczos_norm(runs)
     c = (b_sup + mu_ne) / 2.0
     e = (b_sup - mu_ne) / 2.0
 

@@ -63,6 +63,7 @@ Bounds lanczos_bounds(const std::vector<double>& alpha, const std::vector<double
   Bounds b;
   b.b_sup = -INFINITY;
   b.mu_1 = INFINITY;
+  b.norm_lower = 0.0;
   std::vector<std::pair<double, double>> nodes;  // (theta, weight)
   if (run_len) run_len->assign(nv, 0);
   for (int r = 0; r < nv; ++r) {
@@ -89,6 +90,7 @@ Bounds lanczos_bounds(const std::vector<double>& alpha, const std::vector<double
     sym_eig_small(t, len, th, y);
     b.b_sup = std::max(b.b_sup, th[len - 1] + std::fabs(beta[(size_t)(len - 1) * nv + r]));
     b.mu_1 = std::min(b.mu_1, th[0]);
+    b.norm_lower = std::max(b.norm_lower, std::max(std::fabs(th[0]), std::fabs(th[len - 1])));
     for (int j = 0; j < len; ++j) nodes.emplace_back(th[j], y[j] * y[j] / nv);
   }
   // density of states: smallest node where n * cumulative weight reaches n_e

@@ -10,6 +10,7 @@ namespace chase {
 
 struct Bounds {
   double b_sup, mu_1, mu_ne;
+  double norm_lower;  // largest Ritz value in magnitude: a lower bound of ||H||_2
 };
 
 // One step of Eq. (3): X_s = alpha (H - gamma I) X_{s-1} + beta X_{s-2}.

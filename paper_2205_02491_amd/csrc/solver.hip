@@ -568,7 +568,9 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   stats.t_lanczos = secs(T0, T1);
   const double b_sup = bd.b_sup;
   double mu_1 = bd.mu_1, mu_ne = bd.mu_ne;
-  const double norm_est = std::max(std::fabs(bd.mu_1), std::fabs(bd.b_sup));
+  // residuals relative to a lower bound of ||H||_2, so that res <= tol
+  // guarantees ||H v - theta v|| <= tol ||H||_2
+  const double norm_est = bd.norm_lower > 0 ? bd.norm_lower : std::fabs(bd.b_sup);
 
   const bool mixed = o.filter_prec == CHASE_PREC_FP32;
   const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
@@ -776,10 +778,16 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     const Sizes sz = sizes(dtype, n, nev, nex, o);
     size_t fr = 0, tot = 0;
     CHASE_HIP(hipMemGetInfo(&fr, &tot));
-    if (sz.total > fr)
-      throw Error(CHASE_ERR_NOMEM, "workspace of " + std::to_string(sz.total) +
+    const size_t h32_bytes = (size_t)n * n * h->esz / 2;
+    const size_t need_min = sz.total - (o.filter_prec == CHASE_PREC_FP32 ? h32_bytes : 0);
+    if (need_min > fr)
+      throw Error(CHASE_ERR_NOMEM, "workspace of " + std::to_string(need_min) +
                                        " bytes exceeds free device memory (" +
                                        std::to_string(fr) + ")");
+    // the low-precision copy of H is optional: without it the FP32 products
+    // round H's entries while staging them in LDS
+    const bool with_h32 = o.filter_prec == CHASE_PREC_FP32 &&
+                          sz.total + ((size_t)1 << 30) <= fr;
     const int64_t ne = h->ne;
     h->V = dev_alloc(h, (size_t)n * ne * h->esz);
     h->W = dev_alloc(h, (size_t)n * ne * h->esz);
@@ -810,7 +818,7 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     h->lz.alpha = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
     h->lz.beta = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
     if (o.filter_prec == CHASE_PREC_FP32) {
-      h->H32 = dev_alloc(h, (size_t)n * n * h->esz / 2);
+      if (with_h32) h->H32 = dev_alloc(h, h32_bytes);
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));

@@ -14,6 +14,7 @@ void shim_bounds(const double* alpha, const double* beta, int nv, int steps, lon
   out3[0] = bd.b_sup;
   out3[1] = bd.mu_1;
   out3[2] = bd.mu_ne;
+  out3[3] = bd.norm_lower;
   for (int r = 0; r < nv; ++r) lens[r] = l[r];
 }
 

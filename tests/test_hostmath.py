@@ -56,12 +56,13 @@ def test_lanczos_bounds_match_oracle(shim, kind):
     for r, (ar, br) in enumerate(runs):
         a[: len(ar), r] = ar
         b[: len(br), r] = br       # entries past an early stop stay 0
-    out = np.zeros(3)
+    out = np.zeros(4)
     lens = (ctypes.c_int * nv)()
     shim.shim_bounds(_pd(np.ascontiguousarray(a)), _pd(np.ascontiguousarray(b)), nv, steps, n, ne,
                      _pd(out), lens)
     assert list(lens) == [len(ar) for ar, _ in runs]
-    np.testing.assert_allclose(out, [b_ref, m1_ref, mne_ref], rtol=0, atol=1e-13)
+    np.testing.assert_allclose(out, [b_ref, m1_ref, mne_ref, oracle.lanczos_norm(runs)], rtol=0,
+                               atol=1e-13)
 
 
 def test_chebyshev_coefficients_match_oracle(shim):

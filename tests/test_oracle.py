@@ -127,6 +127,7 @@ def test_lanczos_full_length_exact_quadrature():
     th, y = oracle.tridiag_eig(a, b)
     np.testing.assert_allclose(th, lam, atol=1e-12)
     np.testing.assert_allclose(np.abs(y[0]) ** 2, 1 / n, atol=1e-12)
+    assert abs(oracle.lanczos_norm(runs) - np.max(np.abs(lam))) < 1e-12
     for n_e in (1, 5, 11, 23):
         b_sup, mu_1, mu_ne, _ = oracle.spectral_bounds(h, s[:, None], n, n_e, reorth=True)
         assert abs(mu_ne - lam[n_e - 1]) < 1e-12
@@ -151,6 +152,8 @@ def test_lanczos_bounds_enclose_spectrum(kind):
         assert b_sup >= lam[-1] - 1e-12          # Zhou-Li upper bound
         assert mu_1 >= lam[0] - 1e-12            # Ritz values interlace
         assert mu_1 <= mu_ne <= b_sup
+        nrm = oracle.lanczos_norm(runs)   # residual normalisation: a lower bound
+        assert 0.5 * np.max(np.abs(lam)) <= nrm <= np.max(np.abs(lam)) + 1e-12
         for a, b in runs:
             assert len(a) == 25
 
