@@ -23,6 +23,15 @@ sys.path.insert(0, ROOT)
 METRIC = "solve s @resid≤1e-10 & filter TFLOP/s (% MFMA peak), FP64 vs mixed"
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 
+# HBM bytes per filter launch from rocprofv3 PMC runs (FETCH_SIZE x 2.0 and
+# WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), valid only for the GEMM
+# source they were measured on (sha256 prefix of csrc/gemm.hip).
+MEASURED_TRAFFIC = {
+    ("geometric20k", "fp64"): {"fetch_gb": 34.12, "write_gb": 0.416, "columns": 1300,
+                               "gemm_sha256": "329b3baf9993b111",
+                               "source": "profiles/filter_fp64_geometric20k_hbm_traffic.md"},
+}
+
 WORKLOADS = {
     "geometric20k": dict(kind="geometric", n=20000, nev=1000, nex=300, deg=20, tol=1e-10),
     "cluster121_30k": dict(kind="cluster121", n=30000, nev=1500, nex=500, deg=20, tol=1e-10),
@@ -178,6 +187,10 @@ def main():
     ap.add_argument("--prec", default="both", choices=["fp64", "fp32", "both"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--gen-elementary", action="store_true",
+                    help="build Q from 64 elementary reflectors (no factorization) with the "
+                         "workload's spectrum; for counter-collection runs, where rocprofv3 "
+                         "--pmc crashes inside the dense QR of the usual generator")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte "
                          "counters of rocprofv3 --pmc)")
@@ -212,6 +225,12 @@ def main():
     t0 = time.perf_counter()
     if wl["kind"] == "reflectors":
         prob = gen.make_torch_reflectors(n, nev, nex, device="cuda")
+    elif args.gen_elementary:
+        lam_w = {"geometric": lambda: gen.spectrum_geometric_low(
+                     n, gen.rng(gen.CFG_GEO20K, gen.SLOT_LAMBDA), 1200 if n == 20000 else (nev + nex) * 12 // 13),
+                 "cluster121": lambda: gen.spectrum_121_cluster(
+                     n, gen.rng(gen.CFG_MIXED30K, gen.SLOT_LAMBDA), nev + nex)}[wl["kind"]]()
+        prob = gen.make_torch_reflectors(n, nev, nex, nrefl=64, width=1, device="cuda", lam=lam_w)
     else:
         prob = gen.make_torch(wl["kind"], n, nev, nex, device="cuda")
     torch.cuda.synchronize()
@@ -279,6 +298,15 @@ def main():
             "avg_launch_ms": r["avg_launch_ms"], "flops_per_launch": r["flops_per_launch"]}
     if main_prec == "fp32":
         roof["executed_frac"] = 0.75 * r["filter_tflops"] / peak
+    tr = MEASURED_TRAFFIC.get((args.workload, main_prec))
+    if tr is not None:
+        import hashlib
+        src = os.path.join(ROOT, "paper_2205_02491_amd", "csrc", "gemm.hip")
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        if sha == tr["gemm_sha256"]:
+            roof["traffic"] = (tr["fetch_gb"] + tr["write_gb"]) * 1e9
+            roof["traffic_unit"] = "bytes per launch (%d columns)" % tr["columns"]
+            roof["traffic_source"] = tr["source"]
     out = {
         "metric": METRIC, "value": r["solve_s"], "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["solve_s"] * 1e3,

@@ -232,7 +232,8 @@ def make_torch(kind: str, n: int, nev: int, nex: int, device="cuda", cplx=True,
 
 
 def make_torch_reflectors(n=100000, nev=2000, nex=600, nrefl=8, width=256, device="cuda",
-                          block=4096, n_lanczos=4, cfg=CFG_HUGE100K, deg=20, tol=1e-10):
+                          block=4096, n_lanczos=4, cfg=CFG_HUGE100K, deg=20, tol=1e-10,
+                          lam=None):
     """H = Q diag(lam) Q^H with Q = R_1 R_2 ... R_nrefl, R_j = I - 2 U_j U_j^H a
     block reflector (U_j: n x width, orthonormal columns from the QR of a
     seeded Gaussian), lam i.i.d. U[-1, 1].  H (complex128, n x n, row-major
@@ -242,15 +243,20 @@ def make_torch_reflectors(n=100000, nev=2000, nex=600, nrefl=8, width=256, devic
     applies Q or Q^H to a block using the factored form."""
     import torch
 
-    lam = spectrum_uniform_iid(n, rng(cfg, SLOT_LAMBDA))
+    if lam is None:
+        lam = spectrum_uniform_iid(n, rng(cfg, SLOT_LAMBDA))
     g = torch.Generator(device=device)
     g.manual_seed(BASE_SEED + 10 * cfg + SLOT_Q)
     us = []
     for _ in range(nrefl):
         z = torch.randn((n, width), generator=g, dtype=torch.complex128, device=device)
-        u, _r = torch.linalg.qr(z)
-        us.append(u.contiguous())
-        del z, _r
+        if width == 1:  # elementary reflector: no factorization needed
+            us.append((z / torch.linalg.vector_norm(z)).contiguous())
+        else:
+            u, _r = torch.linalg.qr(z)
+            us.append(u.contiguous())
+            del _r
+        del z
     lam_t = torch.tensor(lam, dtype=torch.float64, device=device)
     H = torch.empty((n, n), dtype=torch.complex128, device=device)
     for j0 in range(0, n, block):
