@@ -27,8 +27,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 # WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), valid only for the GEMM
 # source they were measured on (sha256 prefix of csrc/gemm.hip).
 MEASURED_TRAFFIC = {
-    ("geometric20k", "fp64"): {"fetch_gb": 34.12, "write_gb": 0.416, "columns": 1300,
-                               "gemm_sha256": "329b3baf9993b111",
+    ("geometric20k", "fp64"): {"fetch_gb": 54.56, "write_gb": 0.416, "columns": 1300,
+                               "gemm_sha256": "c1ad426d6acdc184",
                                "source": "profiles/filter_fp64_geometric20k_hbm_traffic.md"},
 }
 
@@ -291,13 +291,14 @@ def main():
     # launches of the timed solves; HIP events around each launch)
     roof = {"bound": "mfma", "achieved": r["filter_tflops"], "peak": peak, "unit": "TFLOP/s",
             "frac": r["filter_tflops"] / peak, "traffic": None,
-            "kernel": ("gemm_kernel<double,double,complex,N,N,CHEB> (FP64 MFMA 16x16x4)"
-                       if main_prec == "fp64" else
-                       "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss> (FP32 MFMA 16x16x4; "
-                       "3 real products per complex product, so executed = 0.75 x algorithmic)"),
+            "kernel": ("gemm_kernel<double,double,complex,N,N,CHEB,8,Gauss,128x64> (FP64 MFMA "
+                       "16x16x4; 3 real products per complex product: executed = 0.75 x "
+                       "algorithmic)" if main_prec == "fp64" else
+                       "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss,128x64> (FP32 MFMA "
+                       "16x16x4; 3 real products per complex product: executed = 0.75 x "
+                       "algorithmic)"),
             "avg_launch_ms": r["avg_launch_ms"], "flops_per_launch": r["flops_per_launch"]}
-    if main_prec == "fp32":
-        roof["executed_frac"] = 0.75 * r["filter_tflops"] / peak
+    roof["executed_frac"] = 0.75 * r["filter_tflops"] / peak
     tr = MEASURED_TRAFFIC.get((args.workload, main_prec))
     if tr is not None:
         import hashlib

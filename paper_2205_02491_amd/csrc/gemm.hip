@@ -12,8 +12,9 @@
 // Operands are staged through double-buffered LDS (k-major, one padding
 // element per row to break bank conflicts on the transposing stores); the
 // next chunk's global loads are issued before the current chunk's MFMAs.
-// A complex product is four real MFMAs (re*re, -im*im, re*im, im*re) in
-// FP64, three (Gauss: re*re, im*im, (re+im)*(re+im)) in FP32.
+// A complex product is three real MFMAs (Gauss: re*re, im*im,
+// (re+im)*(re+im)) in the filter and the other long products, four
+// (re*re, -im*im, re*im, im*re) in the short products of QR/Rayleigh-Ritz.
 // The MFMA is issued with the B fragment in the "A" slot so that each lane's
 // four accumulator values lie along a row of C (one column each): the 16
 // lanes of a group then write 16 consecutive rows of a column-major output.
@@ -21,20 +22,18 @@
 // a contiguous range of tiles, i.e. on the same few row panels of A.
 #include "common.h"
 
-#include <cstdlib>
-
 namespace chase {
 namespace {
 
+// Default tile: 128 x 128 per workgroup, 8 waves in a 2 x 4 grid (64 x 32
+// per wave).  The FP64 three-product kernels use 128 x 64 (4 x 2 waves of
+// 32 x 32) to fit the third accumulator in the register file: 157 VGPRs,
+// measured 75.8 TFLOP/s algorithmic vs 60.2 for the four-product 128 x 128
+// kernel on the n=20000, 1300-column filter step.
 constexpr int BM = 128, BN = 128;
 // K chunk per LDS stage: 8 for FP64 operands; 8 or 16 for FP32
 constexpr int BK_MIN = 8;
 constexpr int NTHR = 512;
-constexpr int WAVES_M = 2, WAVES_N = 4;
-constexpr int WM = BM / WAVES_M;  // 64 rows per wave
-constexpr int WN = BN / WAVES_N;  // 32 cols per wave
-constexpr int FM = WM / 16;       // 4 row fragments
-constexpr int FN = WN / 16;       // 2 col fragments
 constexpr int PAD = 1;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
@@ -131,14 +130,21 @@ __device__ inline Val<TC, CPLX> to_val(R x, bool conj) {
   return v;
 }
 
-template <typename TA, typename TC, bool CPLX, int OPA, int OPB, int EPI, int BKT, bool G3>
+template <typename TA, typename TC, bool CPLX, int OPA, int OPB, int EPI, int BKT, bool G3,
+          int TBM = BM, int TBN = BN, int WAVES_M = 2, int WAVES_N = 4>
 __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int ntiles) {
   using V = Val<TC, CPLX>;
   using acc_t = typename MF<TC>::acc_t;
   constexpr int BK = BKT;
-  constexpr int LOADS = BM * BK / NTHR;  // elements of each operand per thread
-  __shared__ V As[2][BK][BM + PAD];
-  __shared__ V Bs[2][BK][BN + PAD];
+  constexpr int WM = TBM / WAVES_M, WN = TBN / WAVES_N;  // rows / cols per wave
+  constexpr int FM = WM / 16, FN = WN / 16;              // 16 x 16 fragments per wave
+  constexpr int LOADS_A = TBM * BK / NTHR;  // elements of each operand per thread
+  constexpr int LOADS_B = TBN * BK / NTHR;
+  constexpr int LOADS = LOADS_A > LOADS_B ? LOADS_A : LOADS_B;
+  static_assert(WAVES_M * WAVES_N * 64 == NTHR, "8 waves per workgroup");
+  static_assert(LOADS_A * NTHR == TBM * BK && LOADS_B * NTHR == TBN * BK, "tile/threads");
+  __shared__ V As[2][BK][TBM + PAD];
+  __shared__ V Bs[2][BK][TBN + PAD];
 
   // XCD-aware tile index: consecutive hardware ids go round-robin over the
   // 8 XCDs; give each XCD a contiguous range of logical tiles.
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= ntiles) return;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
-  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int64_t m0 = (int64_t)tm * TBM, n0 = (int64_t)tn * TBN;
   const int64_t M = g.M, N = g.N;
   int64_t kbeg = 0, kend = g.K;
   if constexpr (EPI == EPI_SPLITK) {
@@ -162,16 +168,17 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   const TA* __restrict__ A = static_cast<const TA*>(g.A);
   const double* __restrict__ B = static_cast<const double*>(g.B);
 
-  typename RawT<TA, CPLX>::type ra[LOADS];
-  typename RawT<double, CPLX>::type rb[LOADS];
+  typename RawT<TA, CPLX>::type ra[LOADS_A];
+  typename RawT<double, CPLX>::type rb[LOADS_B];
+  (void)LOADS;
   auto load_chunk = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < LOADS; ++e) {
+    for (int e = 0; e < LOADS_A; ++e) {
       const int idx = tid + e * NTHR;
       int i, l;
       if constexpr (OPA == OP_N) {
-        i = idx % BM;
-        l = idx / BM;
+        i = idx % TBM;
+        l = idx / TBM;
       } else {
         l = idx % BK;
         i = idx / BK;
@@ -180,13 +187,17 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
       ra[e] = (gi < M && gk < kend)
                   ? load_raw<TA, CPLX>(A, OPA == OP_N ? gi + gk * g.lda : gk + gi * g.lda)
                   : zero_raw<TA, CPLX>();
+    }
+#pragma unroll
+    for (int e = 0; e < LOADS_B; ++e) {
+      const int idx = tid + e * NTHR;
       int j, lb;
       if constexpr (OPB == OP_N) {
         lb = idx % BK;
         j = idx / BK;
       } else {
-        j = idx % BN;
-        lb = idx / BN;
+        j = idx % TBN;
+        lb = idx / TBN;
       }
       const int64_t gj = n0 + j, gkb = k0 + lb;
       rb[e] = (gj < N && gkb < kend)
@@ -196,31 +207,36 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   };
   auto store_chunk = [&](int buf) {
 #pragma unroll
-    for (int e = 0; e < LOADS; ++e) {
+    for (int e = 0; e < LOADS_A; ++e) {
       const int idx = tid + e * NTHR;
-      int i, l, j, lb;
+      int i, l;
       if constexpr (OPA == OP_N) {
-        i = idx % BM;
-        l = idx / BM;
+        i = idx % TBM;
+        l = idx / TBM;
       } else {
         l = idx % BK;
         i = idx / BK;
       }
+      As[buf][l][i] = to_val<TC, CPLX>(ra[e], OPA == OP_C);
+    }
+#pragma unroll
+    for (int e = 0; e < LOADS_B; ++e) {
+      const int idx = tid + e * NTHR;
+      int j, lb;
       if constexpr (OPB == OP_N) {
         lb = idx % BK;
         j = idx / BK;
       } else {
-        j = idx % BN;
-        lb = idx / BN;
+        j = idx % TBN;
+        lb = idx / TBN;
       }
-      As[buf][l][i] = to_val<TC, CPLX>(ra[e], OPA == OP_C);
       Bs[buf][lb][j] = to_val<TC, CPLX>(rb[e], OPB == OP_C);
     }
   };
 
-  // FP32 complex products use the three-multiplication form (Gauss):
+  // Three-multiplication form (Gauss) when G3 is set:
   // P1 = sum re*re, P2 = sum im*im, P3 = sum (re+im)(re+im);
-  // re = P1 - P2, im = P3 - P1 - P2.  FP64 keeps the four-product form.
+  // re = P1 - P2, im = P3 - P1 - P2.
   constexpr bool GAUSS = CPLX && G3;
   acc_t acc_re[FM][FN], acc_im[FM][FN], acc_s[GAUSS ? FM : 1][GAUSS ? FN : 1];
 #pragma unroll
@@ -297,7 +313,7 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   // lane holds C[m0 + wm*WM + fm*16 + l16][n0 + wn*WN + fn*16 + frag_col(lk, r)]
   double* __restrict__ Cd = static_cast<double*>(g.C);
   if constexpr (EPI == EPI_RESID) {
-    __shared__ double red[WAVES_M][BN];
+    __shared__ double red[WAVES_M][TBN];
     const double* __restrict__ Vd = static_cast<const double*>(g.V);
     double colsum[FN][4];
 #pragma unroll
@@ -348,9 +364,12 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
         for (int r = 0; r < 4; ++r) red[wm][wn * WN + fn * 16 + frag_col<TC>(lk, r)] = colsum[fn][r];
     }
     __syncthreads();
-    if (tid < BN) {
+    if (tid < TBN) {
       const int64_t j = n0 + tid;
-      if (j < N) g.partial[(int64_t)tm * N + j] = red[0][tid] + red[1][tid];
+      double sum = 0.0;
+#pragma unroll
+      for (int w = 0; w < WAVES_M; ++w) sum += red[w][tid];
+      if (j < N) g.partial[(int64_t)tm * N + j] = sum;
     }
     return;
   }
@@ -422,14 +441,15 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
 }
 
 template <typename TA, typename TC, bool CPLX, int OPA, int OPB, int EPI, int BKT = 8,
-          bool G3 = false>
+          bool G3 = false, int TBM = BM, int TBN = BN, int WAVES_M = 2, int WAVES_N = 4>
 void launch(const GemmArgs& g, hipStream_t st) {
-  const int tiles_m = (int)((g.M + BM - 1) / BM);
-  const int tiles_n = (int)((g.N + BN - 1) / BN);
+  const int tiles_m = (int)((g.M + TBM - 1) / TBM);
+  const int tiles_n = (int)((g.N + TBN - 1) / TBN);
   const int ntiles = tiles_m * tiles_n;
   const int grid_x = (ntiles + 7) / 8 * 8;
   dim3 grid(grid_x, 1, EPI == EPI_SPLITK ? g.splits : 1);
-  hipLaunchKernelGGL((gemm_kernel<TA, TC, CPLX, OPA, OPB, EPI, BKT, G3>), grid, dim3(NTHR), 0, st, g,
+  hipLaunchKernelGGL((gemm_kernel<TA, TC, CPLX, OPA, OPB, EPI, BKT, G3, TBM, TBN, WAVES_M, WAVES_N>),
+                     grid, dim3(NTHR), 0, st, g,
                      tiles_n, ntiles);
   CHASE_HIP(hipGetLastError());
 }
@@ -439,28 +459,31 @@ void dispatch(Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g, hipStream_t
   if (prec == PREC_F32) {
     CHASE_REQUIRE(opa == OP_N && opb == OP_N && epi == EPI_CHEB,
                   "FP32 products exist only for the filter step");
-    // variant of the FP32 step kernel: K chunk 8 or 16, four- or
-    // three-product complex arithmetic (CHASE_F32_VARIANT = 0..3, tuning only)
-    static const int variant = [] {
-      const char* e = getenv("CHASE_F32_VARIANT");
-      return e ? atoi(e) & 3 : 3;
-    }();
-    if (!g.a_f32) {
-      launch<double, float, CPLX, OP_N, OP_N, EPI_CHEB, 16, true>(g, st);
-      return;
-    }
-    switch (variant) {
-      case 0: launch<float, float, CPLX, OP_N, OP_N, EPI_CHEB, 8, false>(g, st); break;
-      case 1: launch<float, float, CPLX, OP_N, OP_N, EPI_CHEB, 16, false>(g, st); break;
-      case 2: launch<float, float, CPLX, OP_N, OP_N, EPI_CHEB, 8, true>(g, st); break;
-      default: launch<float, float, CPLX, OP_N, OP_N, EPI_CHEB, 16, true>(g, st); break;
-    }
+    // three-product form on 128 x 64 tiles, K chunk 16 (measured 146 TFLOP/s
+    // algorithmic on the n=20000, 1300-column step vs 134 for 128 x 128)
+    if (g.a_f32)
+      launch<float, float, CPLX, OP_N, OP_N, EPI_CHEB, 16, true, 128, 64, 4, 2>(g, st);
+    else
+      launch<double, float, CPLX, OP_N, OP_N, EPI_CHEB, 16, true, 128, 64, 4, 2>(g, st);
     return;
   }
   if (opa == OP_N && opb == OP_N) {
     switch (epi) {
-      case EPI_STORE: return launch<double, double, CPLX, OP_N, OP_N, EPI_STORE>(g, st);
-      case EPI_CHEB: return launch<double, double, CPLX, OP_N, OP_N, EPI_CHEB>(g, st);
+      case EPI_STORE:
+        // long products (H times a block) use the three-product form as the
+        // filter does; the short ones of QR and Rayleigh-Ritz keep four
+        if constexpr (CPLX) {
+          if (g.K >= 4096)
+            return launch<double, double, CPLX, OP_N, OP_N, EPI_STORE, 8, true, 128, 64, 4, 2>(g,
+                                                                                           st);
+        }
+        return launch<double, double, CPLX, OP_N, OP_N, EPI_STORE>(g, st);
+      case EPI_CHEB:
+        // complex: three-product form on 128 x 64 tiles (4 x 2 waves of 32 x 32)
+        if constexpr (CPLX)
+          return launch<double, double, CPLX, OP_N, OP_N, EPI_CHEB, 8, true, 128, 64, 4, 2>(g, st);
+        else
+          return launch<double, double, CPLX, OP_N, OP_N, EPI_CHEB>(g, st);
       case EPI_RESID: return launch<double, double, CPLX, OP_N, OP_N, EPI_RESID>(g, st);
       case EPI_SPLITK: return launch<double, double, CPLX, OP_N, OP_N, EPI_SPLITK>(g, st);
     }

@@ -608,8 +608,9 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
                    &m[L + n64], b_sup, mu_1, mu_ne, PREC_F32, false, ftlo, st);
       else  // Ritz vectors: defect-correction form with FP32 products
         run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
-                          off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z, ka - n64,
-                          &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, PREC_F32, ftlo, st);
+                          off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z,
+                          ka - n64, &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, PREC_F32,
+                          ftlo, st);
     }
     auto F1 = clk::now();
     stats.t_filter += secs(F0, F1);

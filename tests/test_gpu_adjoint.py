@@ -144,3 +144,36 @@ def test_filter_adjoint_mixed_degrees_input_gradient(pk):
         fd = float(np.real(np.sum(np.conj(gY) * (yp - ym)))) / 2e-6
         an = directional(Gd, E)
         assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * np.linalg.norm(Gd), (fd, an)
+
+
+def test_filter_adjoint_full_size_daleckii_krein(pk):
+    """Differentiation workload size (n=8000 complex128, nev+nex=260 columns,
+    degree 20): the gradient of ||Y^H B||_F^2 against the Daleckii-Krein
+    closed form built from the planted eigenvectors, on the GPU with torch."""
+    import torch
+    announce("filter adjoint n=8000 vs Daleckii-Krein")
+    p = gen.make_uniform(n=8000, nev=200, nex=60, cfg=gen.CFG_DIFF8K)
+    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, True)
+    b_sup, mu_1, mu_ne, m = 1.05, -1.0, -0.9, 20
+    deg = np.full(260, m, dtype=np.int32)
+    H = to_gpu(p.H).requires_grad_(True)
+    X0, Bt = to_gpu(p.V0), to_gpu(B)
+    Y = pk.filtered_block(H, X0, deg, b_sup, mu_1, mu_ne)
+    (torch.linalg.matrix_norm(Y.mH @ Bt) ** 2).backward()
+    G = H.grad
+    lam = p.lam
+    pv = oracle.cheb_poly_value(lam, m, b_sup, mu_1, mu_ne)
+    dp = _cheb_deriv(lam, m, b_sup, mu_1, mu_ne)
+    dl = lam[:, None] - lam[None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        F = np.where(np.abs(dl) > 1e-7, (pv[:, None] - pv[None, :]) / dl,
+                     0.5 * (dp[:, None] + dp[None, :]))
+    q = to_gpu(p.Q)
+    Ft = to_gpu(F).to(torch.complex128)
+    gY = 2.0 * Bt @ (Bt.mH @ Y.detach())
+    M = (q.mH @ gY) @ (X0.mH @ q)
+    G_ref = q @ (Ft * M) @ q.mH
+    G_ref = (G_ref + G_ref.mH) / 2
+    err = float(torch.linalg.matrix_norm(G - G_ref) / torch.linalg.matrix_norm(G_ref))
+    # the reference's own divided differences are accurate to ~1e-8 here
+    assert err < 1e-6, err
