@@ -4,8 +4,8 @@ problem, inputs resident in HBM before timing starts.
 
 Default workload: n=20000 complex128, lowest 1200 eigenvalues geometric
 (-1 + 10^(-4(1-i/1200))), the rest uniform in [0,1], Haar Q; nev=1000,
-nex=300, degree 20, tol 1e-10; FP64 filter (and, as a second measurement on
-the same matrix, the mixed FP32/FP64 filter).
+nex=300, degree 20, tol 1e-10; FP64 filter (and, as further measurements on
+the same matrix, the mixed filters: FP32 products, split-BF16 products).
 
 Prints one JSON line (see the README of the bench contract in the design doc).
 """
@@ -21,7 +21,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "solve s @resid≤1e-10 & filter TFLOP/s (% MFMA peak), FP64 vs mixed"
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
+# dense MFMA peaks of one MI355X (TFLOP/s) for the arithmetic each filter
+# mode executes: FP64, FP32, BF16 (split-BF16 runs on the BF16 matrix cores)
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+# executed MFMA FLOPs per algorithmic FLOP (8 per complex multiply-add):
+# three real products per complex product (Gauss) for FP64/FP32, twelve BF16
+# products (four real products x hi*hi, hi*lo, lo*hi) for split-BF16
+EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+KERNEL_NAME = {
+    "fp64": "gemm_kernel<double,double,complex,N,N,CHEB,8,Gauss,128x64> (FP64 MFMA 16x16x4)",
+    "fp32": "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss,128x64> (FP32 MFMA 16x16x4)",
+    "bf16x3": "gemm_bf16x3_kernel<complex> (BF16 MFMA 32x32x16, 256x128 tiles)",
+}
 
 # HBM bytes per filter launch from rocprofv3 PMC runs (FETCH_SIZE x 2.0 and
 # WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), valid only for the GEMM
@@ -184,7 +196,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="geometric20k", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="both", choices=["fp64", "fp32", "both"])
+    ap.add_argument("--prec", default="all", choices=["fp64", "fp32", "bf16x3", "both", "all"],
+                    help="filter modes to time: both = fp64 + fp32, all = fp64 + fp32 + bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--gen-elementary", action="store_true",
@@ -240,11 +253,11 @@ def main():
     lam = prob["lam"]
     norm = max(abs(lam[0]), abs(lam[-1]))
 
-    precs = ["fp64", "fp32"] if args.prec == "both" else [args.prec]
+    precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3"]}.get(args.prec,
+                                                                          [args.prec])
     results = {}
     for prec in precs:
-        opts = pk.default_opts(filter_prec=pk.PREC_FP32 if prec == "fp32" else pk.PREC_FP64,
-                               verbose=1 if args.verbose else 0)
+        opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if args.verbose else 0)
         handle = pk.Handle(n, nev, nex, H.dtype, opts)
         for w in range(args.warmup):
             ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
@@ -291,14 +304,10 @@ def main():
     # launches of the timed solves; HIP events around each launch)
     roof = {"bound": "mfma", "achieved": r["filter_tflops"], "peak": peak, "unit": "TFLOP/s",
             "frac": r["filter_tflops"] / peak, "traffic": None,
-            "kernel": ("gemm_kernel<double,double,complex,N,N,CHEB,8,Gauss,128x64> (FP64 MFMA "
-                       "16x16x4; 3 real products per complex product: executed = 0.75 x "
-                       "algorithmic)" if main_prec == "fp64" else
-                       "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss,128x64> (FP32 MFMA "
-                       "16x16x4; 3 real products per complex product: executed = 0.75 x "
-                       "algorithmic)"),
+            "kernel": KERNEL_NAME[main_prec] + "; executed MFMA FLOPs = %g x algorithmic"
+                      % EXEC_PER_ALGO[main_prec],
             "avg_launch_ms": r["avg_launch_ms"], "flops_per_launch": r["flops_per_launch"]}
-    roof["executed_frac"] = 0.75 * r["filter_tflops"] / peak
+    roof["executed_frac"] = EXEC_PER_ALGO[main_prec] * r["filter_tflops"] / peak
     tr = MEASURED_TRAFFIC.get((args.workload, main_prec))
     if tr is not None:
         import hashlib
@@ -312,7 +321,7 @@ def main():
         "metric": METRIC, "value": r["solve_s"], "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["solve_s"] * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "c128" if main_prec == "fp64" else "c64/c128",
+        "dtype": {"fp64": "c128", "fp32": "c64/c128", "bf16x3": "bf16x3/c128"}[main_prec],
         "data": "synthetic planted-spectrum Hermitian (seeded, generated on the GPU)",
         "config": {"workload": f"{args.workload}", "n": n, "nev": nev, "nex": nex,
                    "degree": wl["deg"], "tol": wl["tol"], "filter": main_prec,
@@ -326,14 +335,19 @@ def main():
         "qr_shifted_passes": r["qr_shifted"], "qr_householder": r["qr_householder"],
         "roofline": roof,
     }
-    if "fp32" in results and main_prec != "fp32":
-        m = results["fp32"]
-        out["mixed"] = {k: m[k] for k in ("solve_s", "converged", "max_resid", "max_eig_err_rel",
-                                          "max_resid_independent",
-                                          "iterations", "matvecs_fp64", "matvecs_low",
-                                          "filter_tflops", "phases", "qr_shifted",
-                                          "qr_householder")}
-        out["mixed"]["speedup_vs_fp64"] = r["solve_s"] / m["solve_s"]
+    for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3")):
+        if low not in results or main_prec == low:
+            continue
+        m = results[low]
+        out[key] = {k: m[k] for k in ("solve_s", "converged", "max_resid", "max_eig_err_rel",
+                                      "max_resid_independent",
+                                      "iterations", "matvecs_fp64", "matvecs_low",
+                                      "filter_tflops", "phases", "qr_shifted",
+                                      "qr_householder")}
+        out[key]["filter_frac_peak"] = m["filter_tflops"] / PEAK_TFLOPS[low]
+        out[key]["filter_executed_frac"] = EXEC_PER_ALGO[low] * m["filter_tflops"] / \
+            PEAK_TFLOPS[low]
+        out[key]["speedup_vs_fp64"] = r["solve_s"] / m["solve_s"]
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         Hh = H.cpu().numpy()

@@ -52,12 +52,22 @@ typedef enum chase_dtype { CHASE_C128 = 0, CHASE_F64 = 1 } chase_dtype;
 
 /* Precision of the filter's matrix products (the rest of the method always
  * runs in FP64).  CHASE_PREC_FP32: complex64/float32 MFMA products with FP32
- * accumulation; the start block is filtered with the plain recurrence, Ritz
- * vectors in the defect-correction form (see chase_filter_ritz), whose
- * rounding error shrinks with the residual; a vector switches to the FP64
- * filter for good if its residual grows tenfold in an iteration, or once it
- * is below switch_tol (> 0). */
-typedef enum chase_prec { CHASE_PREC_FP64 = 0, CHASE_PREC_FP32 = 1 } chase_prec;
+ * accumulation.  CHASE_PREC_BF16X3: split-BF16 products on the BF16 matrix
+ * cores: each value x of H and of the block is carried as hi = bf16(x) and
+ * lo = bf16(x - hi), a real product as hi*hi + hi*lo + lo*hi with FP32
+ * accumulation (about 2^-16 relative per product); the handle keeps the
+ * split of H (n*n*8 bytes complex, n*n*4 real, padded) and of the block.
+ * In both low-precision modes the start block is filtered with the plain
+ * recurrence, Ritz vectors in the defect-correction form (see
+ * chase_filter_ritz), whose rounding error shrinks with the residual; a
+ * vector switches to the FP64 filter for good if its residual grows tenfold
+ * in an iteration, or once it is below switch_tol (> 0).  H must be
+ * Hermitian (the split stores conj(H) = H^T so that rows are contiguous). */
+typedef enum chase_prec {
+  CHASE_PREC_FP64 = 0,
+  CHASE_PREC_FP32 = 1,
+  CHASE_PREC_BF16X3 = 2
+} chase_prec;
 
 typedef struct chase_opts {
   int max_deg;         /* cap of the optimised degree (default 36)           */
@@ -103,7 +113,9 @@ size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex,
  * Requires 1 <= nev, 1 <= nex, nev+nex <= n.  opts may be NULL (defaults).
  * CHASE_ERR_NOMEM if the workspace exceeds the free device memory.  With
  * CHASE_PREC_FP32 the workspace includes a complex64 copy of H when it fits
- * (chase_workspace_bytes counts it); otherwise H is rounded on the fly. */
+ * (chase_workspace_bytes counts it); otherwise H is rounded on the fly.
+ * With CHASE_PREC_BF16X3 the split copies of H and of the block are
+ * required (NOMEM if they do not fit). */
 chase_status chase_create(chase_handle_t* handle, chase_dtype dtype, int64_t n,
                           int nev, int nex, const chase_opts* opts);
 void chase_destroy(chase_handle_t handle);
@@ -137,7 +149,9 @@ chase_status chase_lanczos(chase_handle_t handle, const void* H_dev, int64_t ldh
 /* Chebyshev filter (Eq. (3), scaled so the polynomial is 1 at mu_1, damping
  * [mu_ne, b_sup]).  Column a of X_dev (n x k, ld ldx, in/out) is replaced by
  * p_{m_a}(H) x_a with m_a = degrees_host[a]: even, >= 2, non-decreasing in a.
- * prec: chase_prec.  record_tape=1 keeps every intermediate block on the
+ * prec: chase_prec (CHASE_PREC_BF16X3 needs a handle created with
+ * filter_prec = CHASE_PREC_BF16X3, else CHASE_ERR_ARG; H_dev is split on
+ * every call).  record_tape=1 keeps every intermediate block on the
  * device for chase_filter_adjoint (needs tape memory; CHASE_ERR_NOMEM if it
  * does not fit).  matvecs (may be NULL) receives the matrix-vector count. */
 chase_status chase_filter(chase_handle_t handle, const void* H_dev, int64_t ldh,
@@ -151,7 +165,7 @@ chase_status chase_filter(chase_handle_t handle, const void* H_dev, int64_t ldh,
  * theta_a v_a.  Since (H - gamma I) v = (theta - gamma) v + r, p(H) v =
  * T_m(theta) v + D_m where D follows the three-term recurrence of Eq. (3)
  * started from D_0 = 0 with the extra term alpha_s T_{s-1}(theta) r_a; only
- * D is multiplied by H, so with prec = CHASE_PREC_FP32 the rounding error is
+ * D is multiplied by H, so with a low-precision prec the rounding error is
  * relative to ||r|| rather than ||p(H) v||.  Degrees as in chase_filter.
  * matvecs (may be NULL) receives the number of column products (m_a - 1 per
  * column: the first step needs none). */

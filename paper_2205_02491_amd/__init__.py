@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchase.so")
 
 C128, F64 = 0, 1
-PREC_FP64, PREC_FP32 = 0, 1
+PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC = range(6)
 _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
            4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}
@@ -268,7 +268,8 @@ def chase_filter(H, X, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64, record_tape=
     import torch
     n, k = X.shape
     if handle is None:
-        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1 if k > 1 else 1, H.dtype)
+        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1 if k > 1 else 1, H.dtype,
+                        filter_prec=int(prec))
     buf = _colmajor(X.to(H.dtype))
     deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
     mv = ctypes.c_int64()
@@ -285,7 +286,7 @@ def chase_filter_ritz(H, V, R, theta, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP6
     theta (k) and residuals R = H V - V diag(theta).  Returns (Y, matvecs)."""
     n, k = V.shape
     if handle is None:
-        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1, H.dtype)
+        handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1, H.dtype, filter_prec=int(prec))
     vbuf = _colmajor(V.to(H.dtype))
     rbuf = _colmajor(R.to(H.dtype))
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))

@@ -49,9 +49,11 @@ enum Op { OP_N = 0, OP_C = 1 };
 //   RESID : partial column sums of |AB - lambda_j * V|^2 per row tile
 enum Epi { EPI_STORE = 0, EPI_CHEB = 1, EPI_SPLITK = 2, EPI_RESID = 3 };
 
-// Arithmetic of the products: FP64 (double MFMA) or FP32 (float MFMA,
-// operands rounded to float when staged in LDS, FP32 accumulation).
-enum Prec { PREC_F64 = 0, PREC_F32 = 1 };
+// Arithmetic of the products: FP64 (double MFMA), FP32 (float MFMA,
+// operands rounded to float when staged in LDS, FP32 accumulation) or split
+// BF16 (three BF16 MFMAs per real product on hi/lo splits of both operands,
+// FP32 accumulation; operands in the s8 layout below).
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
 
 struct GemmArgs {
   int64_t M, N, K;
@@ -74,7 +76,36 @@ struct GemmArgs {
   const double* colcoef;
   void* F;
   int64_t ldf;
+  // PREC_BF16X3: s8 splits of the operands (A: T = conj(H) = H^T, columns
+  // padded to S8_COLS_A; B: the block X, columns padded to S8_COLS_B), with
+  // s8_groups 8-row groups per column.  B above stays the FP64 block read by
+  // the epilogue.
+  const void* a_s8;
+  const void* b_s8;
+  int64_t s8_groups;
 };
+
+// ------------------------------------------------------------------ split BF16
+// s8 layout of a K x C matrix: K padded with zero rows to a multiple of
+// S8_KPAD and grouped by 8; group g of column c at byte (c*groups + g)*planes*16
+// holding re_hi[8] re_lo[8] im_hi[8] im_lo[8] (real: hi[8] lo[8]),
+// hi = bf16(x), lo = bf16(x - hi), round to nearest even.
+constexpr int S8_KPAD = 16;
+constexpr int S8_COLS_A = 256;  // row tile of the split-BF16 GEMM
+constexpr int S8_COLS_B = 128;  // column tile of the split-BF16 GEMM
+inline int64_t s8_groups(int64_t K) { return (K + S8_KPAD - 1) / S8_KPAD * (S8_KPAD / 8); }
+inline int64_t s8_pad(int64_t c, int64_t tile) { return (c + tile - 1) / tile * tile; }
+inline size_t s8_bytes(bool cplx, int64_t K, int64_t cols_pad) {
+  return (size_t)s8_groups(K) * (cplx ? 64 : 32) * (size_t)cols_pad;
+}
+// Split the rows x cols FP64 block src (ld lds) into dst (s8 layout, groups
+// per column, cols_pad columns; columns >= cols and rows >= rows are zero).
+// conj: store the conjugate (complex).
+void split_s8(bool cplx, bool conj, const void* src, int64_t lds, int64_t rows, int64_t cols,
+              int64_t cols_pad, void* dst, int64_t groups, hipStream_t st);
+// Filter step C = alpha (A B - gamma B) + beta C [+ colcoef F] with split-BF16
+// products (GemmArgs a_s8, b_s8, s8_groups; M = rows of C, K <= 8*s8_groups).
+void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st);
 
 // Launch the tile GEMM. cplx selects complex (c128) vs real (double) data.
 void gemm(bool cplx, Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g,

@@ -42,7 +42,12 @@ struct chase_handle_s {
   void* tau = nullptr;
   LanczosBufs lz{};
   void* H32 = nullptr;   // low-precision copy of H for the FP32 filter
-  void* Rres = nullptr;  // residual vectors H v - theta v of the active block (FP32 mode)
+  // split-BF16 filter: s8 splits of conj(H) (columns padded to S8_COLS_A)
+  // and of the block being multiplied (ne padded to S8_COLS_B columns)
+  void* Hs8 = nullptr;
+  void* Xs8 = nullptr;
+  int64_t s8_groups = 0;
+  void* Rres = nullptr;  // residual vectors H v - theta v of the active block (mixed modes)
   double* d_coef = nullptr;  // per-step, per-column coefficients of the filter's defect form
   // filter tape (record_tape)
   void* tape = nullptr;
@@ -120,7 +125,11 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
   s.small = (size_t)ne * 8 * 5 + (size_t)gemm_row_tiles(n) * ne * 8 + 64 + (size_t)ne * 4 +
             (size_t)ne * esz;
   s.lz = lanczos_bytes(cplx, n, o.lanczos_vecs, o.lanczos_steps, &s.lz_splits);
-  s.h32 = o.filter_prec == CHASE_PREC_FP32 ? (size_t)n * n * esz / 2 + (size_t)n * ne * esz : 0;
+  if (o.filter_prec == CHASE_PREC_FP32)
+    s.h32 = (size_t)n * n * esz / 2 + (size_t)n * ne * esz;
+  else if (o.filter_prec == CHASE_PREC_BF16X3)
+    s.h32 = s8_bytes(cplx, n, s8_pad(n, S8_COLS_A)) + s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) +
+            (size_t)n * ne * esz;
   s.small += (size_t)(kMaxDegree + 1) * ne * 8;
   s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
   return s;
@@ -132,7 +141,8 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 200, "lanczos_steps out of range");
   CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
-  CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32,
+  CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32 ||
+                    o.filter_prec == CHASE_PREC_BF16X3,
                 "unknown filter_prec");
 }
 
@@ -180,6 +190,31 @@ struct FilterTiming {
   int64_t launches = 0;
 };
 
+Prec to_prec(int p) {
+  return p == CHASE_PREC_BF16X3 ? PREC_BF16X3 : p == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64;
+}
+
+// Split-BF16 operands of one filter step: the block B (n x cols, ld ldb) of
+// g is split into the handle's block buffer; the split of H is the handle's.
+// The split runs outside the timed GEMM window: it is one pass over the
+// block (HBM-bound), the GEMM reads it n/256 times.
+void bf16_operands(chase_handle_s* h, GemmArgs& g, int cols, hipStream_t st) {
+  CHASE_REQUIRE(h->Hs8 && h->Xs8, "split-BF16 products need a handle created with "
+                                  "filter_prec = CHASE_PREC_BF16X3");
+  split_s8(h->cplx, false, g.B, g.ldb, h->n, cols, s8_pad(cols, S8_COLS_B), h->Xs8, h->s8_groups,
+           st);
+  g.a_s8 = h->Hs8;
+  g.b_s8 = h->Xs8;
+  g.s8_groups = h->s8_groups;
+}
+
+// split of conj(H) = H^T (H Hermitian) for the split-BF16 products
+void split_h(chase_handle_s* h, const void* H, int64_t ldh, hipStream_t st) {
+  CHASE_REQUIRE(h->Hs8, "split-BF16 products need a handle created with "
+                        "filter_prec = CHASE_PREC_BF16X3");
+  split_s8(h->cplx, true, H, ldh, h->n, h->n, s8_pad(h->n, S8_COLS_A), h->Hs8, h->s8_groups, st);
+}
+
 // X (n x k, ld ldx) <- p_{m_a}(H) x_a ; Wb (n x k, ld ldw) ping-pong scratch.
 // degrees non-decreasing, even, >= 2.
 void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t ldx, void* Wb,
@@ -221,6 +256,7 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     g.gamma = cf[s - 1].gamma;
     g.beta = cf[s - 1].beta;
     g.a_f32 = a_f32;
+    if (prec == PREC_BF16X3) bf16_operands(h, g, cols, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
     gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
@@ -309,6 +345,7 @@ void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, i
     g.colcoef = h->d_coef + (size_t)s * k + a0;
     g.F = const_cast<char*>(static_cast<const char*>(R)) + (int64_t)a0 * ldr * (int64_t)h->esz;
     g.ldf = ldr;
+    if (prec == PREC_BF16X3) bf16_operands(h, g, cols, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
     gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
@@ -572,9 +609,11 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   // guarantees ||H v - theta v|| <= tol ||H||_2
   const double norm_est = bd.norm_lower > 0 ? bd.norm_lower : std::fabs(bd.b_sup);
 
-  const bool mixed = o.filter_prec == CHASE_PREC_FP32;
+  const bool mixed = o.filter_prec != CHASE_PREC_FP64;
+  const Prec plow = o.filter_prec == CHASE_PREC_BF16X3 ? PREC_BF16X3 : PREC_F32;
   const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
-  if (mixed) to_f32(cplx, H, ldh, h->H32, n, st);
+  if (plow == PREC_F32 && mixed && h->H32) to_f32(cplx, H, ldh, h->H32, n, st);
+  if (plow == PREC_BF16X3) split_h(h, H, ldh, st);
 
   CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
   std::vector<int> m(ne, deg0);
@@ -603,13 +642,13 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       run_filter(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n64, &m[L], b_sup,
                  mu_1, mu_ne, PREC_F64, false, ft64, st);
     if (ka - n64 > 0) {
-      if (it == 0)  // start block: no Ritz pairs yet, plain FP32 products
+      if (it == 0)  // start block: no Ritz pairs yet, plain low-precision products
         run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
-                   &m[L + n64], b_sup, mu_1, mu_ne, PREC_F32, false, ftlo, st);
-      else  // Ritz vectors: defect-correction form with FP32 products
+                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st);
+      else  // Ritz vectors: defect-correction form with low-precision products
         run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
                           off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z,
-                          ka - n64, &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, PREC_F32,
+                          ka - n64, &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, plow,
                           ftlo, st);
     }
     auto F1 = clk::now();
@@ -646,7 +685,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       double rmax = 0;
       for (int a = L; a < ne; ++a) rmax = std::max(rmax, res[a]);
       std::fprintf(stderr,
-                   "chase it %d: filtered %d (%d fp32), locked %d, max_res %.3e, mu1 %.6f, "
+                   "chase it %d: filtered %d (%d low), locked %d, max_res %.3e, mu1 %.6f, "
                    "mune %.6f\n",
                    it + 1, ka, ka - n64, L, rmax, mu_1, mu_ne);
     }
@@ -780,6 +819,8 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     size_t fr = 0, tot = 0;
     CHASE_HIP(hipMemGetInfo(&fr, &tot));
     const size_t h32_bytes = (size_t)n * n * h->esz / 2;
+    // the FP32 copy of H is optional (without it the FP32 products round H
+    // while staging it in LDS); the split-BF16 copies are required
     const size_t need_min = sz.total - (o.filter_prec == CHASE_PREC_FP32 ? h32_bytes : 0);
     if (need_min > fr)
       throw Error(CHASE_ERR_NOMEM, "workspace of " + std::to_string(need_min) +
@@ -820,6 +861,11 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     h->lz.beta = static_cast<double*>(dev_alloc(h, (size_t)steps * nv * 8));
     if (o.filter_prec == CHASE_PREC_FP32) {
       if (with_h32) h->H32 = dev_alloc(h, h32_bytes);
+      h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
+    } else if (o.filter_prec == CHASE_PREC_BF16X3) {
+      h->s8_groups = s8_groups(n);
+      h->Hs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(n, S8_COLS_A)));
+      h->Xs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(ne, S8_COLS_B)));
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
@@ -899,7 +945,10 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     CHASE_REQUIRE(H && X && degrees, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldx >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
-    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32, "unknown precision");
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3,
+                  "unknown precision");
+    CHASE_REQUIRE(prec != CHASE_PREC_BF16X3 || h->Hs8,
+                  "CHASE_PREC_BF16X3 needs a handle created with that filter_prec");
     CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
                       mu_1 < mu_ne && mu_ne < b_sup,
                   "need mu_1 < mu_ne < b_sup");
@@ -912,10 +961,11 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     set_stream(h, st);
     if (record_tape) ensure_tape(h, k, degrees[k - 1]);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
+    if (prec == CHASE_PREC_BF16X3) split_h(h, H, ldh, st);
     FilterTiming ft;
     h->tape_valid = false;
-    run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne,
-               prec == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64, record_tape != 0, ft, st);
+    run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne, to_prec(prec),
+               record_tape != 0, ft, st);
     if (matvecs) *matvecs = ft.matvecs;
   });
 }
@@ -929,7 +979,10 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
     CHASE_REQUIRE(H && V && R && theta && degrees, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldv >= h->n && ldr >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
-    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32, "unknown precision");
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3,
+                  "unknown precision");
+    CHASE_REQUIRE(prec != CHASE_PREC_BF16X3 || h->Hs8,
+                  "CHASE_PREC_BF16X3 needs a handle created with that filter_prec");
     CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
                       mu_1 < mu_ne && mu_ne < b_sup,
                   "need mu_1 < mu_ne < b_sup");
@@ -942,9 +995,10 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
     hipStream_t st = static_cast<hipStream_t>(stream);
     set_stream(h, st);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
+    if (prec == CHASE_PREC_BF16X3) split_h(h, H, ldh, st);
     FilterTiming ft;
     run_filter_defect(h, H, ldh, V, ldv, R, ldr, h->W, h->Z, k, degrees, theta, b_sup, mu_1,
-                      mu_ne, prec == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64, ft, st);
+                      mu_ne, to_prec(prec), ft, st);
     if (matvecs) *matvecs = ft.matvecs;
   });
 }

@@ -59,6 +59,18 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
         assert b_real < b
     o = pk.default_opts(filter_prec=1)
     assert pk.chase_workspace_bytes(20000, 1000, 300, opts=o) >= 20000 ** 2 * 8
+    # split-BF16 mode adds the split of H (rows padded to 16, columns to 256,
+    # 4 bf16 per complex entry), the split of the block (columns padded to
+    # 128) and the residual block
+    for n, nev, nex, cplx in [(30000, 1500, 500, True), (1000, 100, 40, False)]:
+        ne, esz = nev + nex, (16 if cplx else 8)
+        rows = -(-n // 16) * 16
+        per = 8 if cplx else 4
+        extra = rows * per * (-(-n // 256) * 256) + rows * per * (-(-ne // 128) * 128) \
+            + n * ne * esz
+        o3 = pk.default_opts(filter_prec=pk.PREC_BF16X3)
+        b3 = pk.chase_workspace_bytes(n, nev, nex, cplx=cplx, opts=o3)
+        assert b3 - pk.chase_workspace_bytes(n, nev, nex, cplx=cplx) == extra
     assert pk.chase_workspace_bytes(10, 8, 4) == 0      # nev + nex > n
     assert pk.chase_workspace_bytes(10, 0, 4) == 0
 
@@ -75,6 +87,9 @@ def test_create_rejects_bad_sizes_without_gpu():
     o = pk.default_opts(lanczos_vecs=9)
     st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
     assert st == pk.ERR_ARG
+    o = pk.default_opts(filter_prec=3)
+    st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
+    assert st == pk.ERR_ARG and b"filter_prec" in L.chase_last_error()
     assert L.chase_solve(None, None, 0, 0.0, 0, None, None, None, None, 0, None, None,
                          None) == pk.ERR_ARG
     assert L.chase_filter_adjoint(None, None, 0, None, 0, None, 0, None, None) == pk.ERR_ARG

@@ -1,6 +1,6 @@
-"""Mixed-precision filter (FP32 products, FP64 elsewhere, per-column switch
-back to FP64): the final eigenpairs must meet the FP64 bar against the FP64
-oracle."""
+"""Mixed-precision filter (FP32 or split-BF16 products, FP64 elsewhere,
+per-column switch back to FP64): the final eigenpairs must meet the FP64 bar
+against the FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -20,12 +20,13 @@ def pk():
     return pk
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
 @pytest.mark.parametrize("cplx", [True, False])
-def test_mixed_solve_meets_fp64_bar(pk, cplx):
-    announce(f"mixed solve n=1000 cplx={cplx}")
+def test_mixed_solve_meets_fp64_bar(pk, cplx, prec):
+    announce(f"mixed solve n=1000 cplx={cplx} prec={prec}")
     p = gen.make_uniform(n=1000, nev=100, nex=40, cplx=cplx, cfg=21)
     ev_o, v_o, r_o, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
-    o = pk.default_opts(filter_prec=pk.PREC_FP32)
+    o = pk.default_opts(filter_prec=pk.PREC_FP32 if prec == "fp32" else pk.PREC_BF16X3)
     ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
                                       to_gpu(p.S), opts=o)
     assert st["converged"]

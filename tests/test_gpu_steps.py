@@ -118,6 +118,81 @@ def test_filter_ritz_fp32_error_scales_with_residual(pk):
     assert e_d < 1e-9 and e_d < 1e-3 * e_p, (e_d, e_p)
 
 
+# ------------------------------------------------------------------ split BF16
+# Split-BF16 products: hi = bf16(x), lo = bf16(x - hi) carry 16 significant
+# bits; a product a*b is formed as hi*hi + hi*lo + lo*hi (dropped lo*lo and
+# the split remainders: at most 3 * 2^-16 |ab|, typically ~2^-17) with FP32
+# accumulation.  A dot product of random-sign terms then has relative error
+# ~1e-5; over a bounded recurrence of m steps it stays below ~1e-4.
+@pytest.mark.parametrize("cplx", [True, False])
+@pytest.mark.parametrize("n,k", [(810, 64), (1000, 300)])
+def test_filter_bf16x3_error_bound(pk, cplx, n, k):
+    """n not a multiple of 16 (zero-padded K), several 256-row and 128-column
+    tiles with ragged tails, per-column degrees (the active block shrinks)."""
+    announce(f"filter bf16x3 n={n} k={k} cplx={cplx}")
+    h, lam, q, g = _problem(n, cplx, 3000 + n + k + cplx)
+    x = gen.gaussian(g, (n, k), cplx)
+    deg = np.sort(2 * g.integers(1, 6, size=k)).astype(np.int32)
+    b_sup, mu_1, mu_ne = 1.02, -1.0, -0.6
+    y_ref, mv_ref = oracle.chebyshev_filter(h, x, deg, b_sup, mu_1, mu_ne)
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_BF16X3)
+    assert mv == mv_ref
+    y = to_np(y)
+    err = np.linalg.norm(y - y_ref, axis=0) / np.linalg.norm(y_ref, axis=0)
+    assert np.all(err < 1e-4), (err.max(), int(err.argmax()))
+    # really low precision (not an FP64 or FP32 path): typical error ~1e-5
+    assert np.median(err) > 3e-7, np.median(err)
+
+
+def test_filter_bf16x3_closed_form_diagonal(pk):
+    """H = diag(lambda): p(H) x = p(lambda) * x column by column."""
+    announce("filter bf16x3 closed form on diag(lambda)")
+    n, k = 530, 150
+    lam = np.sort(np.random.Generator(np.random.PCG64(15)).uniform(-1, 1, n))
+    x = np.random.Generator(np.random.PCG64(16)).standard_normal((n, k)) + 0j
+    deg = np.full(k, 12, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 1.01, -1.0, -0.7
+    y, _ = pk.chase_filter(to_gpu(np.diag(lam).astype(complex)), to_gpu(x), deg, b_sup, mu_1,
+                           mu_ne, prec=pk.PREC_BF16X3)
+    p = oracle.cheb_poly_value(lam, 12, b_sup, mu_1, mu_ne)
+    ref = p[:, None] * x
+    err = np.linalg.norm(to_np(y) - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert np.all(err < 1e-4), err.max()
+
+
+def test_filter_ritz_bf16x3_error_scales_with_residual(pk):
+    """Defect-correction form with split-BF16 products: error relative to the
+    residual (1e-6 here), so far below the plain split-BF16 filter's."""
+    announce("filter_ritz bf16x3 vs plain bf16x3")
+    n, k = 900, 40
+    h, lam, q, g = _problem(n, True, 2300)
+    v = q[:, :k] + 1e-6 * gen.gaussian(g, (n, k), True)
+    v /= np.linalg.norm(v, axis=0)[None, :]
+    theta = np.real(np.sum(v.conj() * (h @ v), axis=0))
+    r = h @ v - v * theta[None, :]
+    deg = np.full(k, 20, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 1.02, -1.0, lam[60]
+    y_ref, _ = oracle.chebyshev_filter(h, v, deg, b_sup, mu_1, mu_ne)
+    y_d, _ = pk.chase_filter_ritz(to_gpu(h), to_gpu(v), to_gpu(r), theta, deg, b_sup, mu_1,
+                                  mu_ne, prec=pk.PREC_BF16X3)
+    y_p, _ = pk.chase_filter(to_gpu(h), to_gpu(v), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_BF16X3)
+    e_d = rel_err(to_np(y_d), y_ref)
+    e_p = rel_err(to_np(y_p), y_ref)
+    assert e_p > 1e-7
+    assert e_d < 1e-8 and e_d < 1e-3 * e_p, (e_d, e_p)
+
+
+def test_bf16x3_needs_split_handle(pk):
+    """A handle created for FP64 filtering holds no split of H."""
+    n = 300
+    h, lam, q, g = _problem(n, True, 17)
+    x = gen.gaussian(g, (n, 8), True)
+    handle = pk.Handle(n, 6, 2)
+    with pytest.raises(pk.ChaseError):
+        pk.chase_filter(to_gpu(h), to_gpu(x), np.full(8, 4, np.int32), 1.02, -1.0, -0.6,
+                        prec=pk.PREC_BF16X3, handle=handle)
+
+
 # ------------------------------------------------------------------ Lanczos
 @pytest.mark.parametrize("cplx", [True, False])
 def test_lanczos_matches_oracle(pk, cplx):
