@@ -22,12 +22,25 @@
 // lie along one row of C: 32 lanes then write 32 consecutive rows of a
 // column-major output.
 //
-// Workgroup tile 256 rows (of C) x 128 columns, K chunk 16, 512 threads =
-// 8 wave64 in a 4 x 2 grid, each owning 64 x 64 as 2 x 2 fragments of
-// 32 x 32; the chunk is staged through double-buffered LDS with a 16-byte pad
-// per column (144-byte stride: eight lanes reading 16 bytes each hit 32
-// distinct banks).  Workgroup ids are remapped so that each of the 8 XCDs
-// works on a contiguous range of tiles (the same few row panels of H).
+// Workgroup tile 256 rows (of C) x 128 columns, K chunk 16 (one MFMA
+// k-step), 512 threads = 8 wave64 in a 4 x 2 grid, each owning 64 x 64 as
+// 2 x 2 fragments of 32 x 32 (230 VGPRs: two waves per SIMD).  Chunks are
+// copied global -> LDS by the gfx950 direct LDS loads (global_load_lds_dwordx4:
+// lane t of a wave writes 16 bytes at the wave's LDS base + 16 t), one chunk
+// ahead, into two 48 KB stages; the waits are explicit counters before a
+// bare barrier (an LDS release fence would treat the in-flight direct loads
+// as pending LDS stores and wait for all of them).  Each column's chunk is
+// stored unpadded; its 16-byte piece p sits in slot p ^ ((c >> 1) & 7) so
+// the 16 lanes of an LDS read cycle (consecutive columns, one piece) cover
+// all 64 banks.  Workgroup ids are remapped so that each of the 8 XCDs works
+// on a contiguous range of tiles (the same few row panels of H).
+//
+// Measured on one MI355X (n=30000, 2000 columns): 36 ms per step, 400
+// TFLOP/s algorithmic (1.2 PFLOP/s of BF16 MFMA work).  The matrix cores are
+// busy 54% of the time at the clock this kernel runs at (about 1.95 GHz with
+// random operands: power-limited; 2.3 GHz in a pure-MFMA loop); the same
+// MFMA block alone reaches 94% of peak, and the kernel without its global
+// loads 82%.
 #include "common.h"
 
 namespace chase {
@@ -42,6 +55,7 @@ constexpr int TBM = S8_COLS_A;  // rows of C per workgroup (columns of the T spl
 constexpr int TBN = S8_COLS_B;  // columns of C per workgroup (columns of the X split)
 constexpr int NTHR = 512;
 constexpr int KC = S8_KPAD;     // K per chunk = one MFMA k-step
+constexpr int NSTAGE = 2;       // LDS stages
 
 __device__ inline bf8 as_bf8(u4v v) { return __builtin_bit_cast(bf8, v); }
 __device__ inline u4v neg_u4(u4v v) {
@@ -51,16 +65,71 @@ __device__ inline f16v mfma(u4v a, u4v b, f16v c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
 }
 
+// Chebyshev-step epilogue (FP64): out = alpha (acc - gamma X) + beta out
+// [+ colcoef_j F].  Accumulator r of fragment (fi, fj) in lane (l32, h) is
+// C(i0 + wi*32*FI + fi*32 + l32, j0 + wj*32*FJ + fj*32 + 8*(r/4) + 4*h + r%4)
+// (the 32x32x16 MFMA result layout, measured on the hardware).
+template <bool CPLX, int FI = 2, int FJ = 2>
+__device__ inline void epilogue(const GemmArgs& g, const f16v (&acc_re)[FI][FJ],
+                                const f16v (&acc_im)[FI][FJ], int64_t i0, int64_t j0, int wi,
+                                int wj, int l32, int h) {
+  double* __restrict__ Cd = static_cast<double*>(g.C);
+  const double* __restrict__ B = static_cast<const double*>(g.B);
+  const double* __restrict__ Fd = static_cast<const double*>(g.F);
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi) {
+    const int64_t i = i0 + wi * (32 * FI) + fi * 32 + l32;
+    if (i >= g.M) continue;
+#pragma unroll
+    for (int fj = 0; fj < FJ; ++fj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t j = j0 + wj * (32 * FJ) + fj * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        if (j >= g.N) continue;
+        const int64_t o = i + j * g.ldc;
+        double vr = (double)acc_re[fi][fj][r];
+        if constexpr (CPLX) {
+          double vi = (double)acc_im[fi][fj][r];
+          const d2v x = *reinterpret_cast<const d2v*>(B + 2 * (i + j * g.ldb));
+          vr = g.alpha * (vr - g.gamma * x.x);
+          vi = g.alpha * (vi - g.gamma * x.y);
+          if (g.beta != 0.0) {
+            const d2v y = *reinterpret_cast<const d2v*>(Cd + 2 * o);
+            vr += g.beta * y.x;
+            vi += g.beta * y.y;
+          }
+          if (g.colcoef) {
+            const double cj = g.colcoef[j];
+            const d2v f = *reinterpret_cast<const d2v*>(Fd + 2 * (i + j * g.ldf));
+            vr += cj * f.x;
+            vi += cj * f.y;
+          }
+          *reinterpret_cast<d2v*>(Cd + 2 * o) = d2v{vr, vi};
+        } else {
+          vr = g.alpha * (vr - g.gamma * B[i + j * g.ldb]);
+          if (g.beta != 0.0) vr += g.beta * Cd[o];
+          if (g.colcoef) vr += g.colcoef[j] * Fd[i + j * g.ldf];
+          Cd[o] = vr;
+        }
+      }
+  }
+}
+
 template <bool CPLX>
 __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles_n, int ntiles) {
-  constexpr int P = CPLX ? 4 : 2;               // 16-byte planes per 8-row group
-  constexpr int CB = (KC / 8) * P * 16;         // bytes of one column in one chunk
-  constexpr int CS = CB + 16;                   // LDS column stride
-  constexpr int NCOL = TBM + TBN;
+  constexpr int P = CPLX ? 4 : 2;
+  constexpr int CB = (KC / 8) * P * 16;  // bytes of one column in one chunk
   constexpr int PIECES = CB / 16;
-  constexpr int LOADS = NCOL * PIECES / NTHR;
-  static_assert(LOADS * NTHR == NCOL * PIECES, "chunk / threads");
-  __shared__ __attribute__((aligned(16))) char lds[2][NCOL * CS];
+  constexpr int NW = NTHR / 64;
+  constexpr int NCOL = TBM + TBN;
+  constexpr int STAGE = NCOL * CB;
+  constexpr int BLK_COLS = 1024 / CB;    // columns per 1 KB wave load
+  constexpr int NBLK = NCOL / BLK_COLS;
+  constexpr int LOADS = NBLK / NW;       // wave loads per chunk
+  constexpr int WGI = TBM / 64;          // waves along the rows of C
+  static_assert(WGI * (TBN / 64) == NW, "64 x 64 per wave");
+  static_assert(LOADS * NW == NBLK && LOADS <= 15, "chunk / waves, vmcnt immediate");
+  __shared__ __attribute__((aligned(1024))) char lds[NSTAGE * STAGE];
 
   const int per_xcd = gridDim.x >> 3;
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -73,25 +142,27 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wi = wave >> 1, wj = wave & 1;
+  const int wi = wave % WGI, wj = wave / WGI;
   const int l32 = lane & 31, h = lane >> 5;
+  auto slot = [](int c, int p) { return p ^ ((c >> 1) & (PIECES - 1)); };
 
-  u4v rg[LOADS];
-  auto load_chunk = [&](int64_t c) {
+  // lane's column within a 1 KB block; the piece it fetches is the one whose
+  // slot (in its absolute column col0 + bc) is the lane's position lane % PIECES
+  const int bc = lane / PIECES;
+  const char* srcT = Ta + bc * colbytes;
+  const char* srcX = Xb + bc * colbytes;
+  auto issue = [&](int64_t c) {
+    char* base = lds + (int)(c % NSTAGE) * STAGE;
 #pragma unroll
     for (int e = 0; e < LOADS; ++e) {
-      const int idx = tid + e * NTHR;
-      const int col = idx / PIECES, pc = idx - col * PIECES;
-      const char* src = col < TBM ? Ta + col * colbytes : Xb + (col - TBM) * colbytes;
-      rg[e] = *reinterpret_cast<const u4v*>(src + c * CB + pc * 16);
-    }
-  };
-  auto store_chunk = [&](int buf) {
-#pragma unroll
-    for (int e = 0; e < LOADS; ++e) {
-      const int idx = tid + e * NTHR;
-      const int col = idx / PIECES, pc = idx - col * PIECES;
-      *reinterpret_cast<u4v*>(&lds[buf][col * CS + pc * 16]) = rg[e];
+      const int blk = wave * LOADS + e;
+      const int col0 = blk * BLK_COLS;
+      const int pc = slot(col0 + bc, lane % PIECES);  // slot() is an involution in p
+      const char* src = (col0 < TBM ? srcT + (int64_t)col0 * colbytes
+                                    : srcX + (int64_t)(col0 - TBM) * colbytes) + c * CB + pc * 16;
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(base + blk * 1024),
+                                       16, 0, 0);
     }
   };
 
@@ -105,28 +176,31 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
     }
 
   const int64_t nchunks = g.s8_groups / (KC / 8);
-  load_chunk(0);
-  store_chunk(0);
-  __syncthreads();
+  issue(0);
   for (int64_t c = 0; c < nchunks; ++c) {
-    const int buf = (int)(c & 1);
-    const bool more = c + 1 < nchunks;
-    if (more) load_chunk(c + 1);
-    // fragments: lane reads the 16-byte planes of 8-row group h of its column
+    // chunk c has landed (no other loads are in flight); the barrier also
+    // retires every wave's LDS reads of chunk c-1, whose stage chunk c+1
+    // reuses.  Compiler-only memory barriers keep the LDS accesses on their
+    // side of it.
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x70);  // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (c + 1 < nchunks) issue(c + 1);
+    const char* st = lds + (int)(c % NSTAGE) * STAGE;
     u4v tf[2][P], xf[2][P];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
-      const char* pt = &lds[buf][(wi * 64 + f * 32 + l32) * CS + h * P * 16];
-      const char* px = &lds[buf][(TBM + wj * 64 + f * 32 + l32) * CS + h * P * 16];
+      const int ct = wi * 64 + f * 32 + l32;
+      const int cx = TBM + wj * 64 + f * 32 + l32;
 #pragma unroll
       for (int p = 0; p < P; ++p) {
-        tf[f][p] = *reinterpret_cast<const u4v*>(pt + p * 16);
-        xf[f][p] = *reinterpret_cast<const u4v*>(px + p * 16);
+        const int pc = h * P + p;
+        tf[f][p] = *reinterpret_cast<const u4v*>(st + ct * CB + slot(ct, pc) * 16);
+        xf[f][p] = *reinterpret_cast<const u4v*>(st + cx * CB + slot(cx, pc) * 16);
       }
     }
     if constexpr (CPLX) {
-      // C = T X: re = Tr Xr - Ti Xi, im = Tr Xi + Ti Xr; planes 0,1 = re hi/lo,
-      // 2,3 = im hi/lo.  Each product as hi*hi + hi*lo + lo*hi.
 #pragma unroll
       for (int fj = 0; fj < 2; ++fj) {
         const u4v nxi_h = neg_u4(xf[fj][2]), nxi_l = neg_u4(xf[fj][3]);
@@ -161,53 +235,8 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
           acc_re[fi][fj] = re;
         }
     }
-    if (more) store_chunk(buf ^ 1);
-    __syncthreads();
   }
-
-  // ---------------------------------------------------------------- epilogue
-  // accumulator r of fragment (fi, fj) in lane (l32, h):
-  //   row i = i0 + wi*64 + fi*32 + l32, column j = j0 + wj*64 + fj*32 + 8*(r/4) + 4*h + r%4
-  double* __restrict__ Cd = static_cast<double*>(g.C);
-  const double* __restrict__ B = static_cast<const double*>(g.B);
-  const double* __restrict__ Fd = static_cast<const double*>(g.F);
-#pragma unroll
-  for (int fi = 0; fi < 2; ++fi) {
-    const int64_t i = i0 + wi * 64 + fi * 32 + l32;
-    if (i >= g.M) continue;
-#pragma unroll
-    for (int fj = 0; fj < 2; ++fj)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t j = j0 + wj * 64 + fj * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
-        if (j >= g.N) continue;
-        const int64_t o = i + j * g.ldc;
-        double vr = (double)acc_re[fi][fj][r];
-        if constexpr (CPLX) {
-          double vi = (double)acc_im[fi][fj][r];
-          const d2v x = *reinterpret_cast<const d2v*>(B + 2 * (i + j * g.ldb));
-          vr = g.alpha * (vr - g.gamma * x.x);
-          vi = g.alpha * (vi - g.gamma * x.y);
-          if (g.beta != 0.0) {
-            const d2v y = *reinterpret_cast<const d2v*>(Cd + 2 * o);
-            vr += g.beta * y.x;
-            vi += g.beta * y.y;
-          }
-          if (g.colcoef) {
-            const double cj = g.colcoef[j];
-            const d2v f = *reinterpret_cast<const d2v*>(Fd + 2 * (i + j * g.ldf));
-            vr += cj * f.x;
-            vi += cj * f.y;
-          }
-          *reinterpret_cast<d2v*>(Cd + 2 * o) = d2v{vr, vi};
-        } else {
-          vr = g.alpha * (vr - g.gamma * B[i + j * g.ldb]);
-          if (g.beta != 0.0) vr += g.beta * Cd[o];
-          if (g.colcoef) vr += g.colcoef[j] * Fd[i + j * g.ldf];
-          Cd[o] = vr;
-        }
-      }
-  }
+  epilogue<CPLX>(g, acc_re, acc_im, i0, j0, wi, wj, l32, h);
 }
 
 // ------------------------------------------------------------------ split
