@@ -23,6 +23,8 @@ Pin status
       form, brute-force Jacobi on tiny matrices).
   mu_ne from a short Lanczos run : parity unpinned (an estimate by design;
       only its exact limit on a full-length run is pinned).
+  eigvec_adjoint                 : pinned (central finite differences through
+      numpy's eigendecomposition; projector-loss invariance).
 """
 from __future__ import annotations
 
@@ -364,3 +366,30 @@ def jacobi_eigh(A, sweeps=100, tol=1e-15):
     w = np.real(np.diagonal(a)).copy()
     order = np.argsort(w, kind="stable")
     return w[order], v[:, order]
+
+
+def eigvec_adjoint(H, V, lam, G):
+    """Gradient w.r.t. Hermitian H of a real loss L(V) on the lowest m
+    eigenvectors V (n x m, eigenvalues lam ascending, simple) that does not
+    depend on the vectors' phases, given G = dL/dV in torch's complex
+    convention (dL = Re tr(G^H dV)).
+
+    Definition used (first-order perturbation of a simple eigenpair, summed
+    over the full eigendecomposition H = U diag(mu) U^H, which is the slow,
+    plain part): dv_i = sum_{k != i} u_k (u_k^H dH v_i) / (lam_i - mu_k), so
+        dL/dH = sym( sum_i sum_{k != i} u_k (u_k^H g_i) v_i^H / (lam_i - mu_k) ),
+    sym(A) = (A + A^H)/2 (H ranges over Hermitian matrices).  The eigenpair
+    u_i matching v_i is the i-th lowest.  Not in the paper: it extends the
+    eigenvalue adjoint of the library's differentiation to losses on the
+    eigenvectors.  Pinned by central finite differences through numpy's
+    eigendecomposition on gauge-invariant losses."""
+    n, m = V.shape
+    mu, U = np.linalg.eigh(H)
+    C = U.conj().T @ G                      # C[k, i] = u_k^H g_i
+    D = np.zeros_like(C)
+    for i in range(m):
+        for k in range(n):
+            if k != i:
+                D[k, i] = C[k, i] / (lam[i] - mu[k])
+    A = U @ D @ V.conj().T
+    return (A + A.conj().T) / 2

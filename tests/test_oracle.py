@@ -347,3 +347,39 @@ def test_haar_is_unitary_and_planted_is_hermitian():
     h = gen.planted(lam, q)
     assert np.array_equal(h, h.conj().T)
     np.testing.assert_allclose(np.linalg.eigvalsh(h), lam, atol=1e-14)
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_eigvec_adjoint_matches_finite_differences(cplx):
+    """The eigenvector adjoint (first-order perturbation over the full
+    eigendecomposition) against central differences of two phase-invariant
+    losses, computed with numpy's eigendecomposition:
+    L1 = ||V^H B||_F^2 (torch gradient 2 B B^H V) and
+    L2 = sum_i w_i |v_i[0]|^2 (torch gradient 2 w_i v_i[0] at row 0)."""
+    g = np.random.Generator(np.random.PCG64(901 + cplx))
+    n, m = 40, 6
+    A = gen.gaussian(g, (n, n), cplx)
+    H = (A + A.conj().T) / 2
+    B = gen.gaussian(g, (n, 3), cplx)
+    w = g.standard_normal(m)
+
+    def lowest(Hm):
+        mu, U = np.linalg.eigh(Hm)
+        return mu[:m], U[:, :m]
+
+    def loss(Hm):
+        _, V = lowest(Hm)
+        return float(np.linalg.norm(V.conj().T @ B) ** 2 + np.sum(w * np.abs(V[0, :]) ** 2))
+
+    lam, V = lowest(H)
+    G = 2 * B @ (B.conj().T @ V)
+    G[0, :] += 2 * w * V[0, :]
+    dH = oracle.eigvec_adjoint(H, V, lam, G)
+    assert np.allclose(dH, dH.conj().T)
+    h = 1e-6
+    for s in range(3):
+        E = gen.gaussian(g, (n, n), cplx)
+        E = (E + E.conj().T) / 2
+        fd = (loss(H + h * E) - loss(H - h * E)) / (2 * h)
+        an = float(np.real(np.sum(np.conj(dH) * E)))
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1.0), (fd, an)
