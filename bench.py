@@ -124,7 +124,9 @@ def bench_diff(args, wl):
     """Differentiation workload: loss = sum_i w_i lambda_i + ||Y^H B||_F^2 with
     lambda from the solve and Y the filtered start block at frozen bounds and
     degrees; forward + backward time, and a central-difference check of the
-    gradient along seeded Hermitian directions."""
+    gradient along seeded Hermitian directions.  Second case per dtype: the
+    same loss with Y the eigenvector block (eigenvector adjoint), checked
+    against the planted first-order reference gradient."""
     import numpy as np
     import torch
 
@@ -185,6 +187,49 @@ def bench_diff(args, wl):
             "fwd_bwd_s": float(np.median(tf) + np.median(tb)),
             "fd_rel_err_max": float(max(errs)), "iterations": st["iterations"]}
         log(f"diff {'c128' if cplx else 'f64'}: {out['cases']['c128' if cplx else 'f64']}")
+
+        # the same loss with V the eigenvector block itself:
+        # L = sum_i w_i lam_i + ||V^H B||_F^2 (phase invariant), backward through
+        # chase_eigval_adjoint + chase_eigvec_adjoint; checked against the
+        # first-order formula evaluated from the planted eigendecomposition
+        def loss_vec(Hx):
+            lam, V = pk.chase_eigh(Hx, nev, nex, wl["tol"], wl["deg"], V0, S)
+            return (wt * lam).sum() + torch.linalg.matrix_norm(V.mH @ Bt) ** 2
+
+        tf, tb = [], []
+        for k in range(args.warmup + args.steps):
+            H = Hd.clone().requires_grad_(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            L = loss_vec(H)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            L.backward()
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if k >= args.warmup:
+                tf.append(t1 - t0)
+                tb.append(t2 - t1)
+        G = H.grad
+        Q = torch.from_numpy(p.Q).cuda()
+        lamt = torch.from_numpy(p.lam).cuda()
+        Vq = Q[:, :nev]
+        Gv = 2.0 * Bt @ (Bt.mH @ Vq)
+        C = Q.mH @ Gv
+        den = lamt[:nev][None, :] - lamt[:, None]
+        idx = torch.arange(nev, device="cuda")
+        den[idx, idx] = 1.0
+        D = C / den
+        D[idx, idx] = 0.0
+        A = Q @ (D @ Vq.mH) + (Vq * wt[None, :].to(Vq.dtype)) @ Vq.mH
+        ref = (A + A.mH) / 2
+        ref_err = float(torch.linalg.matrix_norm(G - ref) / torch.linalg.matrix_norm(ref))
+        out["cases"][("c128" if cplx else "f64") + "_eigvec"] = {
+            "fwd_s": float(np.median(tf)), "bwd_s": float(np.median(tb)),
+            "fwd_bwd_s": float(np.median(tf) + np.median(tb)),
+            "ref_rel_err": ref_err}
+        log(f"diff eigvec {'c128' if cplx else 'f64'}: "
+            f"{out['cases'][('c128' if cplx else 'f64') + '_eigvec']}")
     out["value"] = out["cases"]["c128"]["fwd_bwd_s"]
     out["ms_per_step"] = out["value"] * 1e3
     return out

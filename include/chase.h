@@ -199,6 +199,33 @@ chase_status chase_eigval_adjoint(chase_handle_t handle, const void* V_dev,
                                   int64_t ldv, int m, const double* g_host,
                                   void* dH_dev, int64_t ldd, void* stream);
 
+/* Adjoint of the eigenvector map, for real losses of the lowest m
+ * eigenvectors that do not depend on each vector's phase (for instance on
+ * V V^H, or on |v_i^H b|).  Not in the paper: it completes the
+ * differentiation of the solver's outputs.  Inputs: H_dev (n x n, ld ldh),
+ * V_dev (n x m, ld ldv) orthonormal eigenvectors of the m lowest, simple
+ * eigenvalues lambda_host[m] (as returned by chase_solve), G_dev (n x m, ld
+ * ldg) the gradient of the loss w.r.t. V in torch's complex convention
+ * (dL = Re tr(G^H dV)).  Accumulates into dH_dev (n x n, ld ldd) the
+ * gradient w.r.t. Hermitian H, from first-order perturbation
+ * dv_i = sum_{k != i} u_k (u_k^H dH v_i) / (lambda_i - mu_k):
+ *   within span(V):  V E V^H, E = Hermitian part of (v_i^H g_j) / (lambda_j - lambda_i)
+ *                    (0 on the diagonal and between equal eigenvalues),
+ *   complement:      (X V^H + V X^H) / 2, (H - lambda_j I) x_j = -(I - V V^H) g_j,
+ *                    x_j orthogonal to V.
+ * The complement systems are positive definite (V spans the lowest
+ * eigenvectors) and are solved together by conjugate gradients, one FP64
+ * GEMM per iteration, until every column's residual is below tol times its
+ * initial residual (checked every 10 iterations); iterations (may be NULL)
+ * receives the count.  CHASE_ERR_NOCONV after max_iter iterations, with
+ * dH_dev unchanged.  Uses the handle's workspace (1 <= m <= nev+nex); the
+ * first call allocates two more n x (nev+nex) blocks in the handle. */
+chase_status chase_eigvec_adjoint(chase_handle_t handle, const void* H_dev, int64_t ldh,
+                                  const void* V_dev, int64_t ldv, int m,
+                                  const double* lambda_host, const void* G_dev, int64_t ldg,
+                                  void* dH_dev, int64_t ldd, double tol, int max_iter,
+                                  int* iterations, void* stream);
+
 /* Adjoint of the last chase_filter call made with record_tape=1: given
  * gY_dev (n x k, ld ldg), the gradient of a real loss w.r.t. the filtered
  * block, accumulate into dH_dev (n x n, ld ldd) the gradient w.r.t. H

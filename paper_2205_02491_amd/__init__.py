@@ -28,8 +28,8 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
 
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
             "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
-            "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_filter_adjoint",
-            "chase_last_error"]
+            "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_eigvec_adjoint",
+            "chase_filter_adjoint", "chase_last_error"]
 
 
 class ChaseError(RuntimeError):
@@ -101,6 +101,9 @@ def lib():
     L.chase_eigval_adjoint.restype = ci
     L.chase_filter_adjoint.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
     L.chase_filter_adjoint.restype = ci
+    L.chase_eigvec_adjoint.argtypes = [vp, vp, i64, vp, i64, ci, pd, vp, i64, vp, i64, cd, ci,
+                                       ctypes.POINTER(ctypes.c_int), vp]
+    L.chase_eigvec_adjoint.restype = ci
     L.chase_last_error.argtypes = []
     L.chase_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -338,6 +341,25 @@ def chase_eigval_adjoint(V, g, dH, handle=None):
     return dH
 
 
+def chase_eigvec_adjoint(H, V, lam, G, dH, handle=None, tol=1e-10, max_iter=5000):
+    """dH += dL/dH for a phase-invariant loss of the lowest eigenvectors V
+    (n x m torch tensor, eigenvalues lam ascending) with G = dL/dV (torch's
+    convention), in place on the torch tensor dH (n x n).  Returns the number
+    of conjugate-gradient iterations of the complement solves."""
+    n, m = V.shape
+    if handle is None:
+        handle = Handle(n, m, 1 if m < n - 1 else max(1, n - m), H.dtype)
+    vbuf = _colmajor(V.to(H.dtype))
+    gbuf = _colmajor(G.to(H.dtype))
+    lm = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+    its = ctypes.c_int()
+    _check(lib().chase_eigvec_adjoint(handle.ptr, _dev(H), n, _dev(vbuf), n, m,
+                                      lm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      _dev(gbuf), n, _dev(dH), n, float(tol), int(max_iter),
+                                      ctypes.byref(its), _stream()))
+    return its.value
+
+
 def chase_filter_adjoint(H, gY, dH, handle, want_gX=False):
     """Adjoint of the last recorded chase_filter on `handle`: dH += dL/dH;
     returns dL/dX0 (n x k) if want_gX."""
@@ -355,5 +377,6 @@ from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
            "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
            "chase_rayleigh_ritz",
-           "chase_eigval_adjoint", "chase_filter_adjoint", "ChaseEigh", "chase_eigh",
+           "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint", "ChaseEigh",
+           "chase_eigh",
            "filtered_block", "lib", "EXPORTED"]

@@ -155,6 +155,27 @@ void to_f32(bool cplx, const void* src, int64_t lds, void* dst, int64_t n, hipSt
 void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, int* flags,
                   hipStream_t st);
 
+// Batched conjugate gradients (one system per column of an n x k block):
+// out[j] = Re(x_j^H y_j)
+void col_dots(bool cplx, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t n,
+              int64_t k, double* out, hipStream_t st);
+// Column j is live while rr_j > tol2 rr0_j and pq_j > 0 (converged or
+// broken-down columns are frozen).  Live columns: alpha_j = rr_j / pq_j;
+// X += alpha P; R -= alpha Q; rr_new_j = |r_j|^2; frozen: rr_new_j = rr_j.
+// (all blocks ld `ld`)
+void cg_step(bool cplx, void* X, void* R, const void* P, const void* Q, int64_t ld, int64_t n,
+             int64_t k, const double* rr, const double* rr0, const double* pq, double tol2,
+             double* rr_new, hipStream_t st);
+// Live columns (same test, before the step): beta_j = rr_new_j / rr_j;
+// P = R + beta P; rr = rr_new
+void cg_dir(bool cplx, void* P, const void* R, int64_t ld, int64_t n, int64_t k, double* rr,
+            const double* rr0, const double* pq, double tol2, const double* rr_new,
+            hipStream_t st);
+// E = Hermitian part of the divided-difference matrix M_ij / (lam_j - lam_i)
+// (0 on the diagonal and between equal eigenvalues), k x k
+void sym_divdiff(bool cplx, const void* M, int64_t ldm, const double* lam, int64_t k, void* E,
+                 int64_t lde, hipStream_t st);
+
 // ------------------------------------------------------------------ Lanczos
 struct LanczosBufs {
   void* q_prev;    // n x nv

@@ -472,6 +472,114 @@ __global__ __launch_bounds__(TPB) void lz_normalize_k(const double* __restrict__
   }
 }
 
+// ------------------------------------------------------------------ CG helpers
+// (eigenvector adjoint: batched conjugate gradients, one system per column)
+// Block-wide sum of one value per thread (fixed order: deterministic).
+__device__ inline double block_sum1(double x) {
+  __shared__ double red1[TPB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  __syncthreads();
+  if (lane == 0) red1[wave] = x;
+  __syncthreads();
+  double s = 0;
+  for (int w = 0; w < TPB / 64; ++w) s += red1[w];
+  return s;
+}
+
+// out[j] = Re(x_j^H y_j); one block per column
+template <int W>
+__global__ __launch_bounds__(TPB) void col_dots_k(const double* __restrict__ X, int64_t ldx,
+                                                  const double* __restrict__ Y, int64_t ldy,
+                                                  int64_t n, double* out) {
+  const int64_t j = blockIdx.x;
+  const double* x = X + j * ldx * W;
+  const double* y = Y + j * ldy * W;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n * W; i += TPB) s += x[i] * y[i];
+  s = block_sum1(s);
+  if (threadIdx.x == 0) out[j] = s;
+}
+
+// A column is live while rr > tol2 rr0 and pq > 0.  Iterating a converged
+// column on rounding-level residuals makes p^H A p noise and alpha blow up,
+// so converged (or broken-down) columns are frozen.
+__device__ inline bool cg_live(const double* rr, const double* rr0, const double* pq, double tol2,
+                               int64_t j) {
+  return rr[j] > tol2 * rr0[j] && pq[j] > 0.0;
+}
+
+// live columns: alpha = rr / pq; x += alpha p; r -= alpha q; rr_new = |r|^2
+// (frozen columns: rr_new = rr, nothing else changes)
+template <int W>
+__global__ __launch_bounds__(TPB) void cg_step_k(double* __restrict__ X, double* __restrict__ R,
+                                                 const double* __restrict__ P,
+                                                 const double* __restrict__ Q, int64_t ld,
+                                                 int64_t n, const double* rr, const double* rr0,
+                                                 const double* pq, double tol2, double* rr_new) {
+  const int64_t j = blockIdx.x;
+  if (!cg_live(rr, rr0, pq, tol2, j)) {
+    if (threadIdx.x == 0) rr_new[j] = rr[j];
+    return;
+  }
+  const double a = rr[j] / pq[j];
+  double* x = X + j * ld * W;
+  double* r = R + j * ld * W;
+  const double* p = P + j * ld * W;
+  const double* q = Q + j * ld * W;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n * W; i += TPB) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum1(s);
+  if (threadIdx.x == 0) rr_new[j] = s;
+}
+
+// live columns (same test as cg_step_k, on the values before the step):
+// beta = rr_new / rr; p = r + beta p; rr = rr_new
+template <int W>
+__global__ __launch_bounds__(TPB) void cg_dir_k(double* __restrict__ P,
+                                                const double* __restrict__ R, int64_t ld,
+                                                int64_t n, double* rr, const double* rr0,
+                                                const double* pq, double tol2,
+                                                const double* rr_new) {
+  const int64_t j = blockIdx.x;
+  if (!cg_live(rr, rr0, pq, tol2, j)) return;
+  const double b = rr_new[j] / rr[j];
+  double* p = P + j * ld * W;
+  const double* r = R + j * ld * W;
+  for (int64_t i = threadIdx.x; i < n * W; i += TPB) p[i] = r[i] + b * p[i];
+  __syncthreads();
+  if (threadIdx.x == 0) rr[j] = rr_new[j];
+}
+
+// E(i, j) = (M(i, j) - conj(M(j, i))) / (2 (lam_j - lam_i)) for i != j with
+// distinct eigenvalues, else 0 (k x k)
+template <int W>
+__global__ void sym_divdiff_k(const double* __restrict__ M, int64_t ldm,
+                              const double* __restrict__ lam, int64_t k, double* __restrict__ E,
+                              int64_t lde) {
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < k * k;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % k, j = idx / k;
+    const double d = lam[j] - lam[i];
+    const double scale = fmax(fabs(lam[i]), fabs(lam[j])) + 1e-300;
+    double er = 0.0, ei = 0.0;
+    if (i != j && fabs(d) > 1e-14 * scale) {
+      const double* mij = M + (i + j * ldm) * W;
+      const double* mji = M + (j + i * ldm) * W;
+      er = (mij[0] - mji[0]) / (2.0 * d);
+      if (W == 2) ei = (mij[1] + mji[1]) / (2.0 * d);
+    }
+    double* e = E + (i + j * lde) * W;
+    e[0] = er;
+    if (W == 2) e[1] = ei;
+  }
+}
+
 constexpr int LZ_VEC_BLOCKS = 128;
 
 int lz_splits(int64_t n) {
@@ -659,6 +767,61 @@ void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, i
   dim3 grid(blocks_for(n * W, TPB * 4, 64), (unsigned)(k < 65535 ? k : 65535));
   hipLaunchKernelGGL(check_finite_k, grid, dim3(TPB), 0, st, static_cast<const double*>(X), ldx,
                      n * W, k, W, flags);
+  CHASE_HIP(hipGetLastError());
+}
+
+void col_dots(bool cplx, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t n,
+              int64_t k, double* out, hipStream_t st) {
+  if (k <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(col_dots_k<2>, dim3((unsigned)k), dim3(TPB), 0, st,
+                       static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, n,
+                       out);
+  else
+    hipLaunchKernelGGL(col_dots_k<1>, dim3((unsigned)k), dim3(TPB), 0, st,
+                       static_cast<const double*>(X), ldx, static_cast<const double*>(Y), ldy, n,
+                       out);
+  CHASE_HIP(hipGetLastError());
+}
+
+void cg_step(bool cplx, void* X, void* R, const void* P, const void* Q, int64_t ld, int64_t n,
+             int64_t k, const double* rr, const double* rr0, const double* pq, double tol2,
+             double* rr_new, hipStream_t st) {
+  if (k <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(cg_step_k<2>, dim3((unsigned)k), dim3(TPB), 0, st, static_cast<double*>(X),
+                       static_cast<double*>(R), static_cast<const double*>(P),
+                       static_cast<const double*>(Q), ld, n, rr, rr0, pq, tol2, rr_new);
+  else
+    hipLaunchKernelGGL(cg_step_k<1>, dim3((unsigned)k), dim3(TPB), 0, st, static_cast<double*>(X),
+                       static_cast<double*>(R), static_cast<const double*>(P),
+                       static_cast<const double*>(Q), ld, n, rr, rr0, pq, tol2, rr_new);
+  CHASE_HIP(hipGetLastError());
+}
+
+void cg_dir(bool cplx, void* P, const void* R, int64_t ld, int64_t n, int64_t k, double* rr,
+            const double* rr0, const double* pq, double tol2, const double* rr_new,
+            hipStream_t st) {
+  if (k <= 0) return;
+  if (cplx)
+    hipLaunchKernelGGL(cg_dir_k<2>, dim3((unsigned)k), dim3(TPB), 0, st, static_cast<double*>(P),
+                       static_cast<const double*>(R), ld, n, rr, rr0, pq, tol2, rr_new);
+  else
+    hipLaunchKernelGGL(cg_dir_k<1>, dim3((unsigned)k), dim3(TPB), 0, st, static_cast<double*>(P),
+                       static_cast<const double*>(R), ld, n, rr, rr0, pq, tol2, rr_new);
+  CHASE_HIP(hipGetLastError());
+}
+
+void sym_divdiff(bool cplx, const void* M, int64_t ldm, const double* lam, int64_t k, void* E,
+                 int64_t lde, hipStream_t st) {
+  if (k <= 0) return;
+  const unsigned blocks = (unsigned)blocks_for(k * k, TPB, 4096);
+  if (cplx)
+    hipLaunchKernelGGL(sym_divdiff_k<2>, dim3(blocks), dim3(TPB), 0, st,
+                       static_cast<const double*>(M), ldm, lam, k, static_cast<double*>(E), lde);
+  else
+    hipLaunchKernelGGL(sym_divdiff_k<1>, dim3(blocks), dim3(TPB), 0, st,
+                       static_cast<const double*>(M), ldm, lam, k, static_cast<double*>(E), lde);
   CHASE_HIP(hipGetLastError());
 }
 

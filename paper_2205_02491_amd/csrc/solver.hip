@@ -52,6 +52,7 @@ struct chase_handle_s {
   // filter tape (record_tape)
   void* tape = nullptr;
   size_t tape_bytes = 0;
+  void* adj = nullptr;  // eigenvector adjoint: two n x ne blocks (first use; in allocs)
   std::vector<int> tape_deg;
   std::vector<Coef> tape_coef;
   int tape_k = 0;
@@ -1052,6 +1053,127 @@ chase_status chase_eigval_adjoint(chase_handle_t h, const void* V, int64_t ldv, 
     GemmArgs g = gargs(n, n, m, h->Z, n, V, ldv, dH, ldd);
     g.beta = 1.0;
     gemm(h->cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g, st);
+    CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+chase_status chase_eigvec_adjoint(chase_handle_t h, const void* H, int64_t ldh, const void* V,
+                                  int64_t ldv, int m, const double* lambda_host, const void* G,
+                                  int64_t ldg, void* dH, int64_t ldd, double tol, int max_iter,
+                                  int* iterations, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(H && V && lambda_host && G && dH, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= h->n && ldv >= h->n && ldg >= h->n && ldd >= h->n,
+                  "leading dimension smaller than n");
+    CHASE_REQUIRE(m >= 1 && m <= h->ne && m < h->n, "m must be in [1, nev+nex] and below n");
+    CHASE_REQUIRE(tol > 0 && std::isfinite(tol) && max_iter >= 1, "need tol > 0, max_iter >= 1");
+    for (int i = 0; i < m; ++i)
+      CHASE_REQUIRE(std::isfinite(lambda_host[i]), "eigenvalues must be finite");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    const bool cplx = h->cplx;
+    const int64_t n = h->n, ne = h->ne;
+    const size_t esz = h->esz;
+    if (!h->adj) h->adj = dev_alloc(h, 2 * (size_t)n * ne * esz);
+    // blocks (n x m, ld n): X solution, R residual, P direction, Q = P_perp (H - Lambda) P
+    void* X = h->adj;
+    void* R = off(h->adj, n * ne, esz);
+    void* P = h->W;
+    void* Q = h->Z;
+    double* lam = h->d_evals;
+    double* rr = h->d_coef;
+    double* rr_new = rr + ne;
+    double* pq = rr + 2 * ne;
+    double* rr0 = rr + 3 * ne;
+    h2d_sync(lam, lambda_host, m * 8, st);
+    // M = V^H G (m x m, in G, ld ne)
+    gram(h, V, ldv, G, ldg, n, m, m, h->G, ne, false, st);
+    // Complement: (H - lambda_j) x_j = b_j = -(I - V V^H) g_j with x_j orthogonal
+    // to V.  On that complement H - lambda_j is positive definite (V holds
+    // the lowest eigenvectors), so each column is a conjugate-gradient solve;
+    // the products are one GEMM with the per-column shift in its epilogue,
+    // projected back onto the complement every step.
+    copy_cols(cplx, G, ldg, R, n, n, m, st);
+    {
+      GemmArgs g = gargs(n, m, m, V, ldv, h->G, ne, R, n);  // R = V M - G
+      g.beta = -1.0;
+      gemm(cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
+    }
+    fill_zero(X, n * m * (int64_t)esz, st);
+    copy_cols(cplx, R, n, P, n, n, m, st);
+    col_dots(cplx, R, n, R, n, n, m, rr, st);
+    CHASE_HIP(hipMemcpyAsync(rr0, rr, m * 8, hipMemcpyDeviceToDevice, st));
+    std::vector<double> hr(m), hr0(m);
+    CHASE_HIP(hipMemcpyAsync(hr0.data(), rr0, m * 8, hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    bool done = true;
+    for (int j = 0; j < m; ++j) done = done && hr0[j] == 0.0;
+    int it = 0;
+    while (!done && it < max_iter) {
+      ++it;
+      {  // Q = (H - Lambda) P
+        GemmArgs g = gargs(n, m, n, H, ldh, P, n, nullptr, n);
+        g.lambda = lam;
+        g.V = P;
+        g.ldv = n;
+        g.partial = h->d_partial;
+        g.F = Q;
+        g.ldf = n;
+        gemm(cplx, PREC_F64, OP_N, OP_N, EPI_RESID, g, st);
+      }
+      // Q -= V (V^H Q)
+      gram(h, V, ldv, Q, n, n, m, m, h->R, ne, false, st);
+      {
+        GemmArgs g = gargs(n, m, m, V, ldv, h->R, ne, Q, n);
+        g.alpha = -1.0;
+        g.beta = 1.0;
+        gemm(cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
+      }
+      col_dots(cplx, P, n, Q, n, n, m, pq, st);
+      cg_step(cplx, X, R, P, Q, n, n, m, rr, rr0, pq, tol * tol, rr_new, st);
+      cg_dir(cplx, P, R, n, n, m, rr, rr0, pq, tol * tol, rr_new, st);
+      if (it % 10 == 0 || it == max_iter) {
+        CHASE_HIP(hipMemcpyAsync(hr.data(), rr, m * 8, hipMemcpyDeviceToHost, st));
+        CHASE_HIP(hipStreamSynchronize(st));
+        double worst = 0.0;
+        for (int j = 0; j < m; ++j) {
+          if (!std::isfinite(hr[j])) throw Error(CHASE_ERR_NUMERIC, "non-finite CG residual");
+          if (hr0[j] > 0) worst = std::max(worst, std::sqrt(hr[j] / hr0[j]));
+        }
+        done = worst <= tol;
+      }
+    }
+    if (iterations) *iterations = it;
+    if (!done) throw Error(CHASE_ERR_NOCONV, "eigenvector adjoint: CG did not reach tol");
+    // X -= V (V^H X) (exactly on the complement)
+    gram(h, V, ldv, X, n, n, m, m, h->R, ne, false, st);
+    {
+      GemmArgs g = gargs(n, m, m, V, ldv, h->R, ne, X, n);
+      g.alpha = -1.0;
+      g.beta = 1.0;
+      gemm(cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
+    }
+    // dH += (X V^H + V X^H) / 2
+    {
+      GemmArgs g = gargs(n, n, m, X, n, V, ldv, dH, ldd);
+      g.alpha = 0.5;
+      g.beta = 1.0;
+      gemm(cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g, st);
+      GemmArgs g2 = gargs(n, n, m, V, ldv, X, n, dH, ldd);
+      g2.alpha = 0.5;
+      g2.beta = 1.0;
+      gemm(cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g2, st);
+    }
+    // Within the block: dH += V E V^H, E = Hermitian part of M_ij / (lambda_j - lambda_i)
+    sym_divdiff(cplx, h->G, ne, lam, m, h->R, ne, st);
+    {
+      GemmArgs g = gargs(n, m, m, V, ldv, h->R, ne, Q, n);  // Q = V E
+      gemm(cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
+      GemmArgs g2 = gargs(n, n, m, Q, n, V, ldv, dH, ldd);  // dH += Q V^H
+      g2.beta = 1.0;
+      gemm(cplx, PREC_F64, OP_N, OP_C, EPI_STORE, g2, st);
+    }
     CHASE_HIP(hipStreamSynchronize(st));
   });
 }

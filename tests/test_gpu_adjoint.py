@@ -177,3 +177,88 @@ def test_filter_adjoint_full_size_daleckii_krein(pk):
     err = float(torch.linalg.matrix_norm(G - G_ref) / torch.linalg.matrix_norm(G_ref))
     # the reference's own divided differences are accurate to ~1e-8 here
     assert err < 1e-6, err
+
+
+# ------------------------------------------------------------------ eigenvector adjoint
+@pytest.mark.parametrize("cplx", [True, False])
+def test_eigvec_adjoint_matches_oracle(pk, cplx):
+    """chase_eigvec_adjoint (divided differences within the block,
+    conjugate-gradient solves on the complement) against the oracle's
+    definition (first-order perturbation over the full eigendecomposition),
+    for the exact planted eigenpairs and an arbitrary G."""
+    import torch
+    announce(f"eigvec adjoint vs oracle n=320 cplx={cplx}")
+    n, m = 320, 14
+    g = np.random.Generator(np.random.PCG64(120 + cplx))
+    lam = gen.spectrum_uniform_iid(n, g)
+    q = gen.haar(n, g, cplx)
+    Hn = gen.planted(lam, q)
+    V = q[:, :m]
+    G = gen.gaussian(g, (n, m), cplx)
+    ref = oracle.eigvec_adjoint(Hn, V, lam[:m], G)
+    dH = torch.zeros((n, n), dtype=to_gpu(Hn).dtype, device="cuda")
+    its = pk.chase_eigvec_adjoint(to_gpu(Hn), to_gpu(V), lam[:m], to_gpu(G), dH, tol=1e-12)
+    assert its > 0
+    err = np.linalg.norm(to_np(dH) - ref) / np.linalg.norm(ref)
+    assert err < 1e-8, err
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_eigvec_autograd_matches_finite_differences(pk, cplx):
+    """Loss on eigenvalues and eigenvectors through chase_eigh's backward:
+    L = sum_i w_i lam_i + ||V^H B||_F^2, against central differences of the
+    same loss computed with numpy's eigendecomposition."""
+    import torch
+    announce(f"eigvec autograd FD n=300 cplx={cplx}")
+    p = gen.make_uniform(n=300, nev=12, nex=8, cplx=cplx, cfg=32)
+    g = np.random.Generator(np.random.PCG64(33))
+    w = g.standard_normal(p.nev)
+    B = gen.gaussian(g, (300, 3), cplx)
+    Bt = to_gpu(B)
+    H = to_gpu(p.H).requires_grad_(True)
+    lam, vec = pk.chase_eigh(H, p.nev, p.nex, 1e-12, 20, to_gpu(p.V0), to_gpu(p.S), adj_tol=1e-12)
+    L = (torch.from_numpy(w).cuda() * lam).sum() + torch.linalg.matrix_norm(vec.mH @ Bt) ** 2
+    L.backward()
+    G = to_np(H.grad)
+    assert np.linalg.norm(G - G.conj().T) <= 1e-12 * np.linalg.norm(G)
+
+    def loss_np(Hm):
+        mu, U = np.linalg.eigh(Hm)
+        V = U[:, : p.nev]
+        return float(np.dot(w, mu[: p.nev]) + np.linalg.norm(V.conj().T @ B) ** 2)
+
+    h = 1e-6
+    for s in range(3):
+        E = herm_dir(300, cplx, 140 + s)
+        fd = (loss_np(p.H + h * E) - loss_np(p.H - h * E)) / (2 * h)
+        an = directional(G, E)
+        assert abs(fd - an) <= 1e-6 * max(abs(an), np.linalg.norm(G) * 1e-3), (fd, an)
+
+
+def test_eigvec_adjoint_full_size_planted(pk):
+    """Differentiation workload size (n=8000 complex128, 200 eigenvectors):
+    the adjoint of ||V^H B||_F^2 against the first-order formula evaluated
+    with torch from the planted eigendecomposition (all 8000 pairs)."""
+    import torch
+    announce("eigvec adjoint n=8000 vs planted first-order formula")
+    p = gen.make_uniform(n=8000, nev=200, nex=60, cfg=gen.CFG_DIFF8K)
+    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, True)
+    Q = to_gpu(p.Q)
+    lam = torch.from_numpy(p.lam).cuda()
+    V = Q[:, :200].contiguous()
+    Bt = to_gpu(B)
+    G = 2.0 * Bt @ (Bt.mH @ V)
+    H = to_gpu(p.H)
+    dH = torch.zeros_like(H)
+    its = pk.chase_eigvec_adjoint(H, V, p.lam[:200], G, dH, tol=1e-11)
+    C = Q.mH @ G                                   # C[k, i] = q_k^H g_i
+    den = lam[:200][None, :] - lam[:, None]        # lam_i - mu_k
+    idx = torch.arange(200, device="cuda")
+    den[idx, idx] = 1.0
+    D = C / den
+    D[idx, idx] = 0.0
+    A = Q @ (D @ V.mH)
+    ref = (A + A.mH) / 2
+    err = float(torch.linalg.matrix_norm(dH - ref) / torch.linalg.matrix_norm(ref))
+    print(f"[gpu-case] eigvec adjoint n=8000: {its} CG iterations, rel err {err:.2e}", flush=True)
+    assert err < 1e-6, err
