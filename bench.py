@@ -328,7 +328,11 @@ def main():
         fl = sum(s["filter_flops"] for s in stats)
         kt = sum(s["t_filter_kernels"] for s in stats)
         launches = sum(s["filter_launches"] for s in stats)
+        lz_b = sum(s["lanczos_gemv_bytes"] for s in stats)
+        lz_t = sum(s["t_lanczos_gemv"] for s in stats)
         results[prec] = dict(
+            lanczos_gemv_gbs=lz_b / lz_t / 1e9 if lz_t > 0 else None,
+            lanczos_gemv_ms=lz_t / max(1, sum(s["lanczos_gemv_launches"] for s in stats)) * 1e3,
             solve_s=elapsed / args.steps, converged=bool(st["converged"]),
             max_resid=float(res.max()), max_eig_err_rel=err / norm,
             max_resid_independent=indep,
@@ -379,6 +383,14 @@ def main():
         "max_eig_err_rel": r["max_eig_err_rel"], "phases_s": r["phases"],
         "qr_shifted_passes": r["qr_shifted"], "qr_householder": r["qr_householder"],
         "roofline": roof,
+        # memory-bound step: the Lanczos block GEMV (H read once per launch,
+        # 4 vectors), HIP events around each launch of the timed solves
+        "memory_bound": {"kernel": "lz_gemv_k (Lanczos block GEMV, 4 vectors)", "bound": "hbm",
+                         "achieved": r["lanczos_gemv_gbs"], "peak": 8000.0, "unit": "GB/s",
+                         "frac": (r["lanczos_gemv_gbs"] / 8000.0
+                                  if r["lanczos_gemv_gbs"] else None),
+                         "avg_launch_ms": r["lanczos_gemv_ms"],
+                         "bytes_per_launch": n * n * (16 if H.is_complex() else 8)},
     }
     for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3")):
         if low not in results or main_prec == low:

@@ -95,6 +95,9 @@ typedef struct chase_stats {
   double b_sup, mu_1, mu_ne; /* final spectral bounds                         */
   int qr_shifted;          /* QR passes that needed the shifted variant      */
   int qr_householder;      /* QR calls that fell back to Householder         */
+  double t_lanczos_gemv;   /* summed HIP-event time of the Lanczos block GEMVs */
+  int64_t lanczos_gemv_launches; /* number of Lanczos block GEMV launches   */
+  double lanczos_gemv_bytes; /* bytes of H read by them (one pass per launch) */
 } chase_stats;
 
 typedef struct chase_handle_s* chase_handle_t;

@@ -55,7 +55,9 @@ class Stats(ctypes.Structure):
                 ("t_filter_kernels", ctypes.c_double), ("filter_launches", ctypes.c_int64),
                 ("filter_flops", ctypes.c_double), ("b_sup", ctypes.c_double),
                 ("mu_1", ctypes.c_double), ("mu_ne", ctypes.c_double),
-                ("qr_shifted", ctypes.c_int), ("qr_householder", ctypes.c_int)]
+                ("qr_shifted", ctypes.c_int), ("qr_householder", ctypes.c_int),
+                ("t_lanczos_gemv", ctypes.c_double), ("lanczos_gemv_launches", ctypes.c_int64),
+                ("lanczos_gemv_bytes", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -187,6 +187,7 @@ struct LanczosBufs {
   double* alpha;   // steps x nv
   double* beta;    // steps x nv
   int max_splits;
+  hipEvent_t* gemv_ev = nullptr;  // optional: 2 x steps events around each block GEMV
 };
 void lanczos_run(bool cplx, const void* H, int64_t ldh, int64_t n, const void* S, int nv,
                  int steps, LanczosBufs& b, hipStream_t st);

@@ -258,25 +258,27 @@ constexpr int LZ_ROWS_PER_THREAD = 2;
 constexpr int LZ_ROWS = TPB * LZ_ROWS_PER_THREAD;
 constexpr int LZ_COLS_STAGE = 64;
 
-template <bool CPLX>
+template <bool CPLX, int NV>
 __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, int64_t ldh,
-                                                 int64_t n, const double* __restrict__ Q, int nv,
+                                                 int64_t n, const double* __restrict__ Q,
                                                  double* __restrict__ part, int64_t cols_per) {
+  // NV vectors (compile time: the accumulators stay in registers and the
+  // occupancy high enough to keep HBM busy)
   const int W = CPLX ? 2 : 1;
-  __shared__ double qs[LZ_COLS_STAGE][8][2];
+  __shared__ double qs[LZ_COLS_STAGE][NV][2];
   const int64_t r0 = (int64_t)blockIdx.x * LZ_ROWS;
   const int64_t c0 = (int64_t)blockIdx.y * cols_per;
   const int64_t c1 = c0 + cols_per < n ? c0 + cols_per : n;
-  double accr[LZ_ROWS_PER_THREAD][8], acci[LZ_ROWS_PER_THREAD][8];
+  double accr[LZ_ROWS_PER_THREAD][NV], acci[LZ_ROWS_PER_THREAD][NV];
 #pragma unroll
   for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r)
 #pragma unroll
-    for (int v = 0; v < 8; ++v) accr[r][v] = acci[r][v] = 0.0;
+    for (int v = 0; v < NV; ++v) accr[r][v] = acci[r][v] = 0.0;
 
   for (int64_t cs = c0; cs < c1; cs += LZ_COLS_STAGE) {
     const int ncs = (int)(c1 - cs < LZ_COLS_STAGE ? c1 - cs : LZ_COLS_STAGE);
     __syncthreads();
-    for (int e = threadIdx.x; e < ncs * nv; e += TPB) {
+    for (int e = threadIdx.x; e < ncs * NV; e += TPB) {
       const int c = e % ncs, v = e / ncs;
       const double* q = Q + ((cs + c) + (int64_t)v * n) * W;
       qs[c][v][0] = q[0];
@@ -284,7 +286,8 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
     }
     __syncthreads();
     // 8 columns of H per round: 16 independent 16-byte loads in flight per
-    // thread before the arithmetic that consumes them
+    // thread before the arithmetic that consumes them (16 columns or more
+    // workgroups measured no faster: 5.4 TB/s at n=20000, 4 vectors)
     constexpr int CU = 8;
     int c = 0;
     for (; c + CU <= ncs; c += CU) {
@@ -311,14 +314,12 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
 #pragma unroll
       for (int u = 0; u < CU; ++u)
 #pragma unroll
-        for (int v = 0; v < 8; ++v) {
-          if (v < nv) {
-            const double qr = qs[c + u][v][0], qi = qs[c + u][v][1];
+        for (int v = 0; v < NV; ++v) {
+          const double qr = qs[c + u][v][0], qi = qs[c + u][v][1];
 #pragma unroll
-            for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
-              accr[r][v] += hr[u][r] * qr - hi[u][r] * qi;
-              if (CPLX) acci[r][v] += hr[u][r] * qi + hi[u][r] * qr;
-            }
+          for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
+            accr[r][v] += hr[u][r] * qr - hi[u][r] * qi;
+            if (CPLX) acci[r][v] += hr[u][r] * qi + hi[u][r] * qr;
           }
         }
     }
@@ -337,12 +338,10 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
             hr = hc[i];
           }
 #pragma unroll
-          for (int v = 0; v < 8; ++v) {
-            if (v < nv) {
-              const double qr = qs[c][v][0], qi = qs[c][v][1];
-              accr[r][v] += hr * qr - hi * qi;
-              if (CPLX) acci[r][v] += hr * qi + hi * qr;
-            }
+          for (int v = 0; v < NV; ++v) {
+            const double qr = qs[c][v][0], qi = qs[c][v][1];
+            accr[r][v] += hr * qr - hi * qi;
+            if (CPLX) acci[r][v] += hr * qi + hi * qr;
           }
         }
       }
@@ -352,8 +351,9 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
   for (int r = 0; r < LZ_ROWS_PER_THREAD; ++r) {
     const int64_t i = r0 + threadIdx.x + r * TPB;
     if (i < n) {
-      for (int v = 0; v < nv; ++v) {
-        double* p = part + (((int64_t)blockIdx.y * nv + v) * n + i) * W;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double* p = part + (((int64_t)blockIdx.y * NV + v) * n + i) * W;
         p[0] = accr[r][v];
         if (CPLX) p[1] = acci[r][v];
       }
@@ -584,7 +584,7 @@ constexpr int LZ_VEC_BLOCKS = 128;
 
 int lz_splits(int64_t n) {
   const int64_t row_blocks = (n + LZ_ROWS - 1) / LZ_ROWS;
-  int64_t s = (2048 + row_blocks - 1) / row_blocks;
+  int64_t s = (2048 + row_blocks - 1) / row_blocks;  // ~2048 workgroups
   const int64_t smax = (n + 63) / 64;
   if (s > smax) s = smax;
   if (s > 64) s = 64;
@@ -869,15 +869,32 @@ void lanczos_run(bool cplx, const void* Hv, int64_t ldh, int64_t n, const void* 
       hipLaunchKernelGGL(lz_normalize_k<false>, dim3(vb), dim3(TPB), 0, st, b.nrmp, vb, n, nv, w,
                          dst, beta_out);
   };
+  auto gemv = [&](const double* q) {
+#define CHASE_LZ_GEMV(NVC)                                                                   \
+  if (cplx)                                                                                \
+    hipLaunchKernelGGL((lz_gemv_k<true, NVC>), dim3(row_blocks, splits), dim3(TPB), 0, st, H, \
+                       ldh, n, q, part, cols_per);                                          \
+  else                                                                                     \
+    hipLaunchKernelGGL((lz_gemv_k<false, NVC>), dim3(row_blocks, splits), dim3(TPB), 0, st,   \
+                       H, ldh, n, q, part, cols_per);
+    switch (nv) {
+      case 1: CHASE_LZ_GEMV(1) break;
+      case 2: CHASE_LZ_GEMV(2) break;
+      case 3: CHASE_LZ_GEMV(3) break;
+      case 4: CHASE_LZ_GEMV(4) break;
+      case 5: CHASE_LZ_GEMV(5) break;
+      case 6: CHASE_LZ_GEMV(6) break;
+      case 7: CHASE_LZ_GEMV(7) break;
+      default: CHASE_LZ_GEMV(8) break;
+    }
+#undef CHASE_LZ_GEMV
+  };
   orth(0, nullptr);
   normalize(qcur, nullptr);
   for (int j = 0; j < steps; ++j) {
-    if (cplx)
-      hipLaunchKernelGGL(lz_gemv_k<true>, dim3(row_blocks, splits), dim3(TPB), 0, st, H, ldh, n,
-                         qcur, nv, part, cols_per);
-    else
-      hipLaunchKernelGGL(lz_gemv_k<false>, dim3(row_blocks, splits), dim3(TPB), 0, st, H, ldh, n,
-                         qcur, nv, part, cols_per);
+    if (b.gemv_ev) CHASE_HIP(hipEventRecord(b.gemv_ev[2 * j], st));
+    gemv(qcur);
+    if (b.gemv_ev) CHASE_HIP(hipEventRecord(b.gemv_ev[2 * j + 1], st));
     const double* bprev = j > 0 ? b.beta + (int64_t)(j - 1) * nv : nullptr;
     if (cplx)
       hipLaunchKernelGGL(lz_reduce_k<true>, dim3(vb), dim3(TPB), 0, st, part, splits, n, nv,

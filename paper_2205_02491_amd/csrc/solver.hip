@@ -553,12 +553,27 @@ void check_info(chase_handle_s* h, hipStream_t st, const char* what) {
 
 Bounds do_lanczos(chase_handle_s* h, const void* H, int64_t ldh, const void* S, int nv, int steps,
                   std::vector<double>* a_out, std::vector<double>* b_out, std::vector<int>* lens,
-                  hipStream_t st) {
+                  hipStream_t st, double* gemv_s = nullptr) {
+  while (h->evs.size() < 2 * (size_t)steps) {
+    hipEvent_t e;
+    CHASE_HIP(hipEventCreate(&e));
+    h->evs.push_back(e);
+  }
+  h->lz.gemv_ev = gemv_s ? h->evs.data() : nullptr;
   lanczos_run(h->cplx, H, ldh, h->n, S, nv, steps, h->lz, st);
+  h->lz.gemv_ev = nullptr;
   std::vector<double> a((size_t)steps * nv), b((size_t)steps * nv);
   CHASE_HIP(hipMemcpyAsync(a.data(), h->lz.alpha, a.size() * 8, hipMemcpyDeviceToHost, st));
   CHASE_HIP(hipMemcpyAsync(b.data(), h->lz.beta, b.size() * 8, hipMemcpyDeviceToHost, st));
   CHASE_HIP(hipStreamSynchronize(st));
+  if (gemv_s) {
+    *gemv_s = 0.0;
+    for (int j = 0; j < steps; ++j) {
+      float ms = 0.f;
+      CHASE_HIP(hipEventElapsedTime(&ms, h->evs[2 * j], h->evs[2 * j + 1]));
+      *gemv_s += ms * 1e-3;
+    }
+  }
   for (double x : a)
     if (!std::isfinite(x)) throw Error(CHASE_ERR_NUMERIC, "non-finite Lanczos coefficients");
   Bounds bd = lanczos_bounds(a, b, nv, steps, h->n, h->ne, lens);
@@ -601,7 +616,10 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
 
   // Lanczos spectral bounds
   const int steps = (int)std::min<int64_t>(o.lanczos_steps, n);
-  Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, nullptr, nullptr, nullptr, st);
+  Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, nullptr, nullptr, nullptr, st,
+                         &stats.t_lanczos_gemv);
+  stats.lanczos_gemv_launches = steps;
+  stats.lanczos_gemv_bytes = (double)steps * (double)n * (double)n * (double)h->esz;
   auto T1 = clk::now();
   stats.t_lanczos = secs(T0, T1);
   const double b_sup = bd.b_sup;
