@@ -235,6 +235,62 @@ def bench_diff(args, wl):
     return out
 
 
+def warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm, handle):
+    """One step of a sequence of related problems (the use case the method is
+    built for): H2 = H + E with a seeded Hermitian E of spectral norm
+    1e-5 ||H||_2, solved from the cold start block and from [eigenvectors of
+    H | last nex columns of the cold start block]."""
+    import torch
+
+    n = H.shape[0]
+    if n > 40000:
+        return {"skipped": "the perturbed copy needs two more n x n buffers"}
+    g = torch.Generator(device=H.device)
+    g.manual_seed(20250502)
+    E = torch.randn((n, n), generator=g, dtype=H.dtype, device=H.device)
+    E = (E + E.mH) / 2
+    # ||E||_2 of a Gaussian Hermitian matrix is about sqrt(2 n) times its
+    # entry scale (semicircle edge); a few power steps pin it down
+    x = torch.randn((n, 1), generator=g, dtype=H.dtype, device=H.device)
+    for _ in range(30):
+        x = E @ x
+        x = x / torch.linalg.vector_norm(x)
+    e2 = float(torch.linalg.vector_norm(E @ x))
+    H2 = H + (1e-5 * norm / e2) * E
+    del E
+    v0w = torch.cat([vec, V0[:, nev:]], dim=1).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, rc, stc = pk.chase_solve(H2, nev, nex, wl["tol"], wl["deg"], V0, S, handle=handle)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    evw, _, rw, stw = pk.chase_solve(H2, nev, nex, wl["tol"], wl["deg"], v0w, S, handle=handle)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    # the same warm start with Rayleigh-Ritz on the start block (initial_rr)
+    opts_rr = pk.Opts.from_buffer_copy(handle.opts)
+    opts_rr.initial_rr = 1
+    hrr = pk.Handle(n, nev, nex, H.dtype, opts_rr)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    _, _, rr_res, strr = pk.chase_solve(H2, nev, nex, wl["tol"], wl["deg"], v0w, S, handle=hrr)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    hrr.close()
+    del H2
+    return {"perturbation": "||E||_2 = 1e-5 ||H||_2", "cold_s": t1 - t0, "warm_s": t2 - t1,
+            "speedup": (t1 - t0) / (t2 - t1), "iterations_cold": stc["iterations"],
+            "iterations_warm": stw["iterations"],
+            "matvecs_cold": stc["matvecs_fp64"] + stc["matvecs_low"],
+            "matvecs_warm": stw["matvecs_fp64"] + stw["matvecs_low"],
+            "converged": bool(stc["converged"] and stw["converged"] and strr["converged"]),
+            "max_resid_warm": float(rw.max()),
+            "warm_initial_rr_s": t4 - t3, "speedup_initial_rr": (t1 - t0) / (t4 - t3),
+            "iterations_warm_initial_rr": strr["iterations"],
+            "matvecs_warm_initial_rr": strr["matvecs_fp64"] + strr["matvecs_low"],
+            "max_resid_warm_initial_rr": float(rr_res.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -244,6 +300,10 @@ def main():
     ap.add_argument("--prec", default="all", choices=["fp64", "fp32", "bf16x3", "both", "all"],
                     help="filter modes to time: both = fp64 + fp32, all = fp64 + fp32 + bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-start", action="store_true",
+                    help="also time a sequence step: H + E (||E||_2 = 1e-5 ||H||_2, seeded "
+                         "Hermitian) solved cold and warm-started from the previous "
+                         "eigenvectors, in each timed filter mode")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--gen-elementary", action="store_true",
                     help="build Q from 64 elementary reflectors (no factorization) with the "
@@ -344,6 +404,10 @@ def main():
             phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")},
             qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
             stats=st)
+        if args.warm_start:
+            results[prec]["warm_start"] = warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm,
+                                                          handle)
+            log(f"{prec} warm start: {results[prec]['warm_start']}")
         handle.close()
 
     main_prec = "fp64" if "fp64" in results else precs[0]
@@ -405,6 +469,8 @@ def main():
         out[key]["filter_executed_frac"] = EXEC_PER_ALGO[low] * m["filter_tflops"] / \
             PEAK_TFLOPS[low]
         out[key]["speedup_vs_fp64"] = r["solve_s"] / m["solve_s"]
+    if args.warm_start:
+        out["warm_start"] = {p: results[p]["warm_start"] for p in results}
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         Hh = H.cpu().numpy()

@@ -79,7 +79,12 @@ typedef struct chase_opts {
   int filter_prec;     /* chase_prec (default CHASE_PREC_FP64)                */
   double switch_tol;   /* FP32->FP64 switch residual; <= 0: never           */
   int verbose;         /* 1: one line per iteration on stderr                */
-  int reserved[7];
+  int initial_rr;      /* 1: Rayleigh-Ritz on the start block before the first
+                          filter (warm starts from approximate eigenvectors:
+                          converged pairs lock at once, the first degrees are
+                          optimised, mixed modes use the defect form from the
+                          start).  Not in Algorithm 1; default 0            */
+  int reserved[6];
 } chase_opts;
 
 typedef struct chase_stats {

@@ -43,7 +43,8 @@ class Opts(ctypes.Structure):
                 ("optimize_degree", ctypes.c_int), ("lanczos_steps", ctypes.c_int),
                 ("lanczos_vecs", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("filter_prec", ctypes.c_int), ("switch_tol", ctypes.c_double),
-                ("verbose", ctypes.c_int), ("reserved", ctypes.c_int * 7)]
+                ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
+                ("reserved", ctypes.c_int * 6)]
 
 
 class Stats(ctypes.Structure):

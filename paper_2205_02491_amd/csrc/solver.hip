@@ -142,6 +142,7 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 200, "lanczos_steps out of range");
   CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
+  CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
   CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32 ||
                     o.filter_prec == CHASE_PREC_BF16X3,
                 "unknown filter_prec");
@@ -650,35 +651,10 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   bool converged = false;
   std::vector<int> perm(ne);
   FilterTiming ft64, ftlo;
-  for (int it = 0; it < o.max_iter; ++it) {
-    stats.iterations = it + 1;
-    const int ka = ne - L;
-    // ---- filter (FP64 group first, then the low-precision group)
-    auto F0 = clk::now();
-    int n64 = 0;
-    while (n64 < ka && !low[L + n64]) ++n64;
-    if (n64 > 0)
-      run_filter(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n64, &m[L], b_sup,
-                 mu_1, mu_ne, PREC_F64, false, ft64, st);
-    if (ka - n64 > 0) {
-      if (it == 0)  // start block: no Ritz pairs yet, plain low-precision products
-        run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
-                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st);
-      else  // Ritz vectors: defect-correction form with low-precision products
-        run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
-                          off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z,
-                          ka - n64, &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, plow,
-                          ftlo, st);
-    }
-    auto F1 = clk::now();
-    stats.t_filter += secs(F0, F1);
-    // ---- QR of [Y V]
-    qr_step(h, h->V, n, ne, L, h->W, &stats, st);
-    auto Q1 = clk::now();
-    stats.t_qr += secs(F1, Q1);
-    // ---- Rayleigh-Ritz + residuals on the active part
-    rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
-            &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n);
+  // After Rayleigh-Ritz on the active block [L, L+ka): residuals, precision
+  // switches, locking of the converged prefix, and unless done the bounds,
+  // degrees and sort for the next filter.  Returns true when the solve stops.
+  auto after_rr = [&](int it, int ka, int n64) -> bool {
     check_info(h, st, "Hermitian eigensolver");
     CHASE_HIP(hipMemcpyAsync(&lam[L], h->d_evals, ka * sizeof(double), hipMemcpyDeviceToHost, st));
     std::vector<double> r_new(ka);
@@ -710,9 +686,9 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     }
     if (L >= nev) {
       converged = true;
-      break;
+      return true;
     }
-    if (it + 1 == o.max_iter) break;
+    if (it + 1 == o.max_iter) return true;
     // ---- bounds, degrees, precision groups, sort
     mu_1 = *std::min_element(lam.begin(), lam.end());
     mu_ne = *std::max_element(lam.begin(), lam.end());
@@ -752,6 +728,51 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       gather_cols(cplx, off(h->Rres, (int64_t)L * n, h->esz), n, h->W, n, n, kb, h->d_perm, st);
       copy_cols(cplx, h->W, n, off(h->Rres, (int64_t)L * n, h->esz), n, n, kb, st);
     }
+    return false;
+  };
+  // Optional Rayleigh-Ritz on the start block (an extension of Algorithm 1,
+  // for warm starts from approximate eigenvectors): already converged pairs
+  // lock before any filtering, the first filter uses the degrees optimised
+  // from the start block's residuals, and the mixed modes filter its Ritz
+  // vectors in the defect-correction form from the first pass on.
+  bool have_ritz = false;
+  if (o.initial_rr) {
+    qr_step(h, h->V, n, ne, 0, h->W, &stats, st);
+    rr_step(h, H, ldh, h->V, n, ne, norm_est, h->W, h->Z, &stats.t_rr, &stats.t_resid, st,
+            mixed ? h->Rres : nullptr, n);
+    have_ritz = true;
+    if (after_rr(-1, ne, 0)) stats.iterations = 0;
+  }
+  for (int it = 0; it < o.max_iter && !converged; ++it) {
+    stats.iterations = it + 1;
+    const int ka = ne - L;
+    // ---- filter (FP64 group first, then the low-precision group)
+    auto F0 = clk::now();
+    int n64 = 0;
+    while (n64 < ka && !low[L + n64]) ++n64;
+    if (n64 > 0)
+      run_filter(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, h->W, n, n64, &m[L], b_sup,
+                 mu_1, mu_ne, PREC_F64, false, ft64, st);
+    if (ka - n64 > 0) {
+      if (it == 0 && !have_ritz)  // start block: no Ritz pairs yet, plain low-precision products
+        run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
+                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st);
+      else  // Ritz vectors: defect-correction form with low-precision products
+        run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
+                          off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z,
+                          ka - n64, &m[L + n64], &lam[L + n64], b_sup, mu_1, mu_ne, plow,
+                          ftlo, st);
+    }
+    auto F1 = clk::now();
+    stats.t_filter += secs(F0, F1);
+    // ---- QR of [Y V]
+    qr_step(h, h->V, n, ne, L, h->W, &stats, st);
+    auto Q1 = clk::now();
+    stats.t_qr += secs(F1, Q1);
+    // ---- Rayleigh-Ritz + residuals on the active part
+    rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
+            &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n);
+    if (after_rr(it, ka, n64)) break;
   }
   // ---- output: lowest nev of the locked pairs (or of all pairs on NOCONV)
   const int pool = converged ? L : ne;

@@ -151,3 +151,48 @@ def test_solve_warm_start_sequence(pk):
     # the oracle needs 5366 vs 9960 Matvecs on this sequence
     assert st_w["matvecs_fp64"] < 0.7 * st_c["matvecs_fp64"], (st_w["matvecs_fp64"],
                                                                 st_c["matvecs_fp64"])
+
+
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+def test_solve_warm_start_initial_rayleigh_ritz(pk, prec):
+    """Warm start with Rayleigh-Ritz on the start block (initial_rr): the
+    first filter uses degrees optimised from the start block's residuals, so
+    the perturbed problem needs fewer Matvecs than a cold start (measured
+    0.70x FP64, 0.67x split-BF16 here); the pairs still match the oracle and
+    meet the tolerance."""
+    announce(f"warm start + initial RR n=1000 prec={prec}")
+    p = gen.make_uniform(n=1000, nev=100, nex=40, cfg=15)
+    ev1, vec1, _, _ = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                     to_gpu(p.S))
+    g = np.random.Generator(np.random.PCG64(16))
+    E = gen.gaussian(g, (p.n, p.n), True)
+    H2 = p.H + 1e-5 * (E + E.conj().T) / (2 * np.linalg.norm(E, 2))
+    v0w = np.concatenate([to_np(vec1), p.V0[:, p.nev:]], axis=1)
+    fp = pk.PREC_FP64 if prec == "fp64" else pk.PREC_BF16X3
+    o_cold = pk.default_opts(filter_prec=fp)
+    o_rr = pk.default_opts(filter_prec=fp, initial_rr=1)
+    _, _, _, st_c = pk.chase_solve(to_gpu(H2), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                   to_gpu(p.S), opts=o_cold)
+    ev_w, vec_w, res_w, st_w = pk.chase_solve(to_gpu(H2), p.nev, p.nex, p.tol, p.deg,
+                                              to_gpu(v0w), to_gpu(p.S), opts=o_rr)
+    ev_o, _, _, _ = oracle.solve(H2, p.nev, p.nex, p.tol, 10, v0w, p.S)
+    assert st_w["converged"] and np.all(res_w <= p.tol)
+    assert np.max(np.abs(ev_w - ev_o)) <= 1e-10
+    mv_c = st_c["matvecs_fp64"] + st_c["matvecs_low"]
+    mv_w = st_w["matvecs_fp64"] + st_w["matvecs_low"]
+    assert mv_w < 0.75 * mv_c, (mv_w, mv_c)
+    v = to_np(vec_w)
+    assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) <= 1e-12
+
+
+def test_initial_rr_on_converged_start_block_locks_without_filtering(pk):
+    """A start block that already holds the exact eigenvectors: the initial
+    Rayleigh-Ritz locks them and the solve ends without a filter pass."""
+    announce("initial RR on the exact eigenvectors")
+    p = gen.make_uniform(n=600, nev=30, nex=10, cfg=17)
+    v0 = np.concatenate([p.Q[:, :30], p.V0[:, 30:]], axis=1)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), 30, 10, 1e-10, 20, to_gpu(v0), to_gpu(p.S),
+                                      opts=pk.default_opts(initial_rr=1))
+    assert st["converged"] and st["iterations"] == 0
+    assert st["matvecs_fp64"] == 0 and np.all(res <= 1e-10)
+    assert np.max(np.abs(ev - p.lam[:30])) <= 1e-12
