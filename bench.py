@@ -39,8 +39,8 @@ KERNEL_NAME = {
 # WRITE_SIZE x 1.0, calibrated on a 1 GiB copy), valid only for the GEMM
 # source they were measured on (sha256 prefix of csrc/gemm.hip).
 MEASURED_TRAFFIC = {
-    ("geometric20k", "fp64"): {"fetch_gb": 54.56, "write_gb": 0.416, "columns": 1300,
-                               "gemm_sha256": "c1ad426d6acdc184",
+    ("geometric20k", "fp64"): {"fetch_gb": 54.55, "write_gb": 0.416, "columns": 1300,
+                               "gemm_sha256": "a638f47ae446067a",
                                "source": "profiles/filter_fp64_geometric20k_hbm_traffic.md"},
 }
 
