@@ -83,6 +83,9 @@ struct GemmArgs {
   const void* a_s8;
   const void* b_s8;
   int64_t s8_groups;
+  // PREC_BF16X3: workspace (s8_tail_bytes) for the split-K tail of the
+  // launch; nullptr runs every tile whole
+  float* s8_tail;
 };
 
 // ------------------------------------------------------------------ split BF16
@@ -97,6 +100,12 @@ inline int64_t s8_groups(int64_t K) { return (K + S8_KPAD - 1) / S8_KPAD * (S8_K
 inline int64_t s8_pad(int64_t c, int64_t tile) { return (c + tile - 1) / tile * tile; }
 inline size_t s8_bytes(bool cplx, int64_t K, int64_t cols_pad) {
   return (size_t)s8_groups(K) * (cplx ? 64 : 32) * (size_t)cols_pad;
+}
+// FP32 partial tiles of the split-K tail: at most S8_TAIL_SLOTS (tile, K
+// slice) pairs of S8_COLS_A x S8_COLS_B (re and im for complex).
+constexpr int S8_TAIL_SLOTS = 256;
+inline size_t s8_tail_bytes(bool cplx) {
+  return (size_t)S8_TAIL_SLOTS * S8_COLS_A * S8_COLS_B * (cplx ? 2 : 1) * sizeof(float);
 }
 // Split the rows x cols FP64 block src (ld lds) into dst (s8 layout, groups
 // per column, cols_pad columns; columns >= cols and rows >= rows are zero).

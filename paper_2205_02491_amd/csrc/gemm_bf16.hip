@@ -35,12 +35,23 @@
 // all 64 banks.  Workgroup ids are remapped so that each of the 8 XCDs works
 // on a contiguous range of tiles (the same few row panels of H).
 //
-// Measured on one MI355X (n=30000, 2000 columns): 36 ms per step, 400
-// TFLOP/s algorithmic (1.2 PFLOP/s of BF16 MFMA work).  The matrix cores are
-// busy 54% of the time at the clock this kernel runs at (about 1.95 GHz with
-// random operands: power-limited; 2.3 GHz in a pure-MFMA loop); the same
-// MFMA block alone reaches 94% of peak, and the kernel without its global
-// loads 82%.
+// One workgroup fits a CU (98 KB of LDS), so a launch runs in rounds of one
+// tile per CU and a last round that is at most half full would leave most
+// of the chip idle.  Those tiles are run as a split-K tail instead: each in
+// up to (CUs / tiles) K slices, every slice writing its FP32 accumulators to
+// a workspace, and a second kernel sums the slices in FP64 and applies the
+// Chebyshev-step update.
+//
+// Measured on one MI355X (n=30000, 2000 columns, 1888 tiles): 32.9 ms per
+// step with the tail (34.3 ms without), 438 TFLOP/s algorithmic (1.3
+// PFLOP/s of BF16 MFMA work).  n=20000 with 1300 columns: 10.4 ms (11.2 ms
+// without the tail).  The matrix cores are busy 54% of the time at the
+// clock this kernel runs at (about 1.95 GHz with random operands:
+// power-limited; 2.3 GHz in a pure-MFMA loop); the same MFMA block alone
+// reaches 94% of peak, and the kernel without its global loads 82%.
+#include <algorithm>
+#include <atomic>
+
 #include "common.h"
 
 namespace chase {
@@ -55,7 +66,7 @@ constexpr int TBM = S8_COLS_A;  // rows of C per workgroup (columns of the T spl
 constexpr int TBN = S8_COLS_B;  // columns of C per workgroup (columns of the X split)
 constexpr int NTHR = 512;
 constexpr int KC = S8_KPAD;     // K per chunk = one MFMA k-step
-constexpr int NSTAGE = 2;       // LDS stages
+constexpr int NSTAGE = 2;       // LDS stages (stage of chunk c: c & 1)
 
 __device__ inline bf8 as_bf8(u4v v) { return __builtin_bit_cast(bf8, v); }
 __device__ inline u4v neg_u4(u4v v) {
@@ -65,17 +76,46 @@ __device__ inline f16v mfma(u4v a, u4v b, f16v c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
 }
 
-// Chebyshev-step epilogue (FP64): out = alpha (acc - gamma X) + beta out
-// [+ colcoef_j F].  Accumulator r of fragment (fi, fj) in lane (l32, h) is
-// C(i0 + wi*32*FI + fi*32 + l32, j0 + wj*32*FJ + fj*32 + 8*(r/4) + 4*h + r%4)
-// (the 32x32x16 MFMA result layout, measured on the hardware).
+// Chebyshev-step update of one element (FP64): out = alpha (acc - gamma X)
+// + beta out [+ colcoef_j F].
+template <bool CPLX>
+__device__ inline void cheb_elem(const GemmArgs& g, int64_t i, int64_t j, double vr, double vi) {
+  double* __restrict__ Cd = static_cast<double*>(g.C);
+  const double* __restrict__ B = static_cast<const double*>(g.B);
+  const double* __restrict__ Fd = static_cast<const double*>(g.F);
+  const int64_t o = i + j * g.ldc;
+  if constexpr (CPLX) {
+    const d2v x = *reinterpret_cast<const d2v*>(B + 2 * (i + j * g.ldb));
+    vr = g.alpha * (vr - g.gamma * x.x);
+    vi = g.alpha * (vi - g.gamma * x.y);
+    if (g.beta != 0.0) {
+      const d2v y = *reinterpret_cast<const d2v*>(Cd + 2 * o);
+      vr += g.beta * y.x;
+      vi += g.beta * y.y;
+    }
+    if (g.colcoef) {
+      const double cj = g.colcoef[j];
+      const d2v f = *reinterpret_cast<const d2v*>(Fd + 2 * (i + j * g.ldf));
+      vr += cj * f.x;
+      vi += cj * f.y;
+    }
+    *reinterpret_cast<d2v*>(Cd + 2 * o) = d2v{vr, vi};
+  } else {
+    vr = g.alpha * (vr - g.gamma * B[i + j * g.ldb]);
+    if (g.beta != 0.0) vr += g.beta * Cd[o];
+    if (g.colcoef) vr += g.colcoef[j] * Fd[i + j * g.ldf];
+    Cd[o] = vr;
+  }
+}
+
+// Epilogue of a whole tile.  Accumulator r of fragment (fi, fj) in lane
+// (l32, h) is C(i0 + wi*32*FI + fi*32 + l32, j0 + wj*32*FJ + fj*32 +
+// 8*(r/4) + 4*h + r%4) (the 32x32x16 MFMA result layout, measured on the
+// hardware).
 template <bool CPLX, int FI = 2, int FJ = 2>
 __device__ inline void epilogue(const GemmArgs& g, const f16v (&acc_re)[FI][FJ],
                                 const f16v (&acc_im)[FI][FJ], int64_t i0, int64_t j0, int wi,
                                 int wj, int l32, int h) {
-  double* __restrict__ Cd = static_cast<double*>(g.C);
-  const double* __restrict__ B = static_cast<const double*>(g.B);
-  const double* __restrict__ Fd = static_cast<const double*>(g.F);
 #pragma unroll
   for (int fi = 0; fi < FI; ++fi) {
     const int64_t i = i0 + wi * (32 * FI) + fi * 32 + l32;
@@ -86,37 +126,43 @@ __device__ inline void epilogue(const GemmArgs& g, const f16v (&acc_re)[FI][FJ],
       for (int r = 0; r < 16; ++r) {
         const int64_t j = j0 + wj * (32 * FJ) + fj * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
         if (j >= g.N) continue;
-        const int64_t o = i + j * g.ldc;
-        double vr = (double)acc_re[fi][fj][r];
-        if constexpr (CPLX) {
-          double vi = (double)acc_im[fi][fj][r];
-          const d2v x = *reinterpret_cast<const d2v*>(B + 2 * (i + j * g.ldb));
-          vr = g.alpha * (vr - g.gamma * x.x);
-          vi = g.alpha * (vi - g.gamma * x.y);
-          if (g.beta != 0.0) {
-            const d2v y = *reinterpret_cast<const d2v*>(Cd + 2 * o);
-            vr += g.beta * y.x;
-            vi += g.beta * y.y;
-          }
-          if (g.colcoef) {
-            const double cj = g.colcoef[j];
-            const d2v f = *reinterpret_cast<const d2v*>(Fd + 2 * (i + j * g.ldf));
-            vr += cj * f.x;
-            vi += cj * f.y;
-          }
-          *reinterpret_cast<d2v*>(Cd + 2 * o) = d2v{vr, vi};
-        } else {
-          vr = g.alpha * (vr - g.gamma * B[i + j * g.ldb]);
-          if (g.beta != 0.0) vr += g.beta * Cd[o];
-          if (g.colcoef) vr += g.colcoef[j] * Fd[i + j * g.ldf];
-          Cd[o] = vr;
-        }
+        cheb_elem<CPLX>(g, i, j, (double)acc_re[fi][fj][r],
+                        CPLX ? (double)acc_im[fi][fj][r] : 0.0);
       }
   }
 }
 
-template <bool CPLX>
-__global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles_n, int ntiles) {
+// Split-K tail: the FP32 partial tile of one K slice, column-major within
+// the tile (TBM rows), re then im.
+template <bool CPLX, int FI = 2, int FJ = 2>
+__device__ inline void store_partial(float* __restrict__ ws, const f16v (&acc_re)[FI][FJ],
+                                     const f16v (&acc_im)[FI][FJ], int wi, int wj, int l32,
+                                     int h) {
+#pragma unroll
+  for (int fi = 0; fi < FI; ++fi) {
+    const int il = wi * (32 * FI) + fi * 32 + l32;
+#pragma unroll
+    for (int fj = 0; fj < FJ; ++fj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int jl = wj * (32 * FJ) + fj * 32 + 8 * (r >> 2) + 4 * h + (r & 3);
+        ws[jl * TBM + il] = acc_re[fi][fj][r];
+        if constexpr (CPLX) ws[TBM * TBN + jl * TBM + il] = acc_im[fi][fj][r];
+      }
+  }
+}
+
+// Launch plan: tiles [0, ntiles) whole, then (split-K tail) tiles
+// [tile0, tile0 + rem) in K slices of cps chunks, partial tiles to ws.
+struct TailPlan {
+  int tile0, rem, slices;
+  int64_t cps;
+  float* ws;
+};
+
+template <bool CPLX, bool SPLIT>
+__global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles_n, int ntiles,
+                                                           TailPlan tp) {
   constexpr int P = CPLX ? 4 : 2;
   constexpr int CB = (KC / 8) * P * 16;  // bytes of one column in one chunk
   constexpr int PIECES = CB / 16;
@@ -131,9 +177,15 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
   static_assert(LOADS * NW == NBLK && LOADS <= 15, "chunk / waves, vmcnt immediate");
   __shared__ __attribute__((aligned(1024))) char lds[NSTAGE * STAGE];
 
+  // Workgroup ids are remapped so that each XCD takes a contiguous range of
+  // work items.  Whole tiles: item = tile.  Tail: item = slice * rem + tile
+  // offset, so one XCD works on one K slice of neighbouring tiles.
   const int per_xcd = gridDim.x >> 3;
-  const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-  if (t >= ntiles) return;
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= (SPLIT ? tp.rem * tp.slices : ntiles)) return;
+  const int slice = SPLIT ? u / tp.rem : 0;
+  const int tr = SPLIT ? u - slice * tp.rem : 0;
+  const int t = SPLIT ? tp.tile0 + tr : u;
   const int tm = t / tiles_n, tn = t - tm * tiles_n;
   const int64_t i0 = (int64_t)tm * TBM, j0 = (int64_t)tn * TBN;
   const int64_t colbytes = g.s8_groups * P * 16;
@@ -152,7 +204,7 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
   const char* srcT = Ta + bc * colbytes;
   const char* srcX = Xb + bc * colbytes;
   auto issue = [&](int64_t c) {
-    char* base = lds + (int)(c % NSTAGE) * STAGE;
+    char* base = lds + (int)(c & 1) * STAGE;
 #pragma unroll
     for (int e = 0; e < LOADS; ++e) {
       const int blk = wave * LOADS + e;
@@ -176,8 +228,10 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
     }
 
   const int64_t nchunks = g.s8_groups / (KC / 8);
-  issue(0);
-  for (int64_t c = 0; c < nchunks; ++c) {
+  const int64_t cb = SPLIT ? slice * tp.cps : 0;
+  const int64_t ce = SPLIT ? (cb + tp.cps < nchunks ? cb + tp.cps : nchunks) : nchunks;
+  issue(cb);
+  for (int64_t c = cb; c < ce; ++c) {
     // chunk c has landed (no other loads are in flight); the barrier also
     // retires every wave's LDS reads of chunk c-1, whose stage chunk c+1
     // reuses.  Compiler-only memory barriers keep the LDS accesses on their
@@ -186,8 +240,8 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
     __builtin_amdgcn_s_waitcnt(0x70);  // vmcnt(0) lgkmcnt(0)
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    if (c + 1 < nchunks) issue(c + 1);
-    const char* st = lds + (int)(c % NSTAGE) * STAGE;
+    if (c + 1 < ce) issue(c + 1);
+    const char* st = lds + (int)(c & 1) * STAGE;
     u4v tf[2][P], xf[2][P];
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
@@ -236,7 +290,36 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
         }
     }
   }
-  epilogue<CPLX>(g, acc_re, acc_im, i0, j0, wi, wj, l32, h);
+  if constexpr (SPLIT)
+    store_partial<CPLX>(tp.ws + (int64_t)u * (CPLX ? 2 : 1) * (TBM * TBN), acc_re, acc_im, wi, wj,
+                        l32, h);
+  else
+    epilogue<CPLX>(g, acc_re, acc_im, i0, j0, wi, wj, l32, h);
+}
+
+// Split-K tail: sum the slices' partial tiles (FP64) and apply the
+// Chebyshev-step update, one element per thread, rows fastest.
+template <bool CPLX>
+__global__ void tail_finish_k(GemmArgs g, int tiles_n, TailPlan tp) {
+  constexpr int TE = TBM * TBN;
+  const int64_t total = (int64_t)tp.rem * TE;
+  for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int tr = (int)(idx / TE);
+    const int e = (int)(idx - (int64_t)tr * TE);
+    const int jl = e / TBM, il = e - jl * TBM;
+    const int t = tp.tile0 + tr;
+    const int tm = t / tiles_n, tn = t - tm * tiles_n;
+    const int64_t i = (int64_t)tm * TBM + il, j = (int64_t)tn * TBN + jl;
+    if (i >= g.M || j >= g.N) continue;
+    double vr = 0.0, vi = 0.0;
+    for (int sl = 0; sl < tp.slices; ++sl) {
+      const float* p = tp.ws + ((int64_t)sl * tp.rem + tr) * (CPLX ? 2 : 1) * TE + e;
+      vr += (double)p[0];
+      if constexpr (CPLX) vi += (double)p[TE];
+    }
+    cheb_elem<CPLX>(g, i, j, vr, vi);
+  }
 }
 
 // ------------------------------------------------------------------ split
@@ -314,6 +397,17 @@ void split_s8(bool cplx, bool conj, const void* src, int64_t lds, int64_t rows, 
   CHASE_HIP(hipGetLastError());
 }
 
+int device_cus() {
+  static std::atomic<int> cached[16];
+  int dev = 0;
+  CHASE_HIP(hipGetDevice(&dev));
+  if (dev < 16 && cached[dev].load() > 0) return cached[dev].load();
+  int n = 0;
+  CHASE_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+  if (dev < 16) cached[dev].store(n);
+  return n;
+}
+
 void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
   CHASE_REQUIRE(g.a_s8 && g.b_s8 && g.s8_groups > 0 && g.s8_groups % (S8_KPAD / 8) == 0,
@@ -322,14 +416,54 @@ void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st) {
   const int tiles_m = (int)((g.M + TBM - 1) / TBM);
   const int tiles_n = (int)((g.N + TBN - 1) / TBN);
   const int ntiles = tiles_m * tiles_n;
-  const int grid_x = (ntiles + 7) / 8 * 8;
-  if (cplx)
-    hipLaunchKernelGGL(gemm_bf16x3_kernel<true>, dim3(grid_x), dim3(NTHR), 0, st, g, tiles_n,
-                       ntiles);
-  else
-    hipLaunchKernelGGL(gemm_bf16x3_kernel<false>, dim3(grid_x), dim3(NTHR), 0, st, g, tiles_n,
-                       ntiles);
-  CHASE_HIP(hipGetLastError());
+  const int64_t nchunks = g.s8_groups / (KC / 8);
+  // One workgroup per CU (LDS-bound), so a launch runs in rounds of `cus`
+  // tiles.  A last round filled at most half is run as a split-K tail: its
+  // tiles in K slices of at least kMinChunks chunks on the idle CUs, the FP32
+  // partial tiles summed by a second kernel.
+  constexpr int64_t kMinChunks = 16;
+  const int cus = device_cus();
+  TailPlan tp{0, 0, 1, nchunks, g.s8_tail};
+  if (g.s8_tail && cus > 0) {
+    const int rem = ntiles % cus;
+    if (rem > 0 && 2 * rem <= cus) {
+      const int64_t want = std::min<int64_t>(
+          {(int64_t)(cus / rem), (int64_t)(S8_TAIL_SLOTS / rem), nchunks / kMinChunks});
+      if (want >= 2) {
+        tp.cps = (nchunks + want - 1) / want;
+        tp.slices = (int)((nchunks + tp.cps - 1) / tp.cps);
+        tp.rem = rem;
+        tp.tile0 = ntiles - rem;
+      }
+    }
+  }
+  const int whole = ntiles - tp.rem;
+  if (whole > 0) {
+    const int grid_x = (whole + 7) / 8 * 8;
+    if (cplx)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, whole, tp);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, whole, tp);
+    CHASE_HIP(hipGetLastError());
+  }
+  if (tp.rem > 0) {
+    const int items = tp.rem * tp.slices;
+    const int grid_x = (items + 7) / 8 * 8;
+    const int64_t elems = (int64_t)tp.rem * TBM * TBN;
+    const unsigned fin = (unsigned)std::min<int64_t>((elems + 255) / 256, 8192);
+    if (cplx) {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, ntiles, tp);
+      hipLaunchKernelGGL(tail_finish_k<true>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
+    } else {
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, ntiles, tp);
+      hipLaunchKernelGGL(tail_finish_k<false>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
+    }
+    CHASE_HIP(hipGetLastError());
+  }
 }
 
 }  // namespace chase

@@ -46,6 +46,7 @@ struct chase_handle_s {
   // and of the block being multiplied (ne padded to S8_COLS_B columns)
   void* Hs8 = nullptr;
   void* Xs8 = nullptr;
+  float* s8tail = nullptr;  // FP32 partial tiles of the GEMM's split-K tail
   int64_t s8_groups = 0;
   void* Rres = nullptr;  // residual vectors H v - theta v of the active block (mixed modes)
   double* d_coef = nullptr;  // per-step, per-column coefficients of the filter's defect form
@@ -130,7 +131,7 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
     s.h32 = (size_t)n * n * esz / 2 + (size_t)n * ne * esz;
   else if (o.filter_prec == CHASE_PREC_BF16X3)
     s.h32 = s8_bytes(cplx, n, s8_pad(n, S8_COLS_A)) + s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) +
-            (size_t)n * ne * esz;
+            s8_tail_bytes(cplx) + (size_t)n * ne * esz;
   s.small += (size_t)(kMaxDegree + 1) * ne * 8;
   s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
   return s;
@@ -208,6 +209,7 @@ void bf16_operands(chase_handle_s* h, GemmArgs& g, int cols, hipStream_t st) {
   g.a_s8 = h->Hs8;
   g.b_s8 = h->Xs8;
   g.s8_groups = h->s8_groups;
+  g.s8_tail = h->s8tail;
 }
 
 // split of conj(H) = H^T (H Hermitian) for the split-BF16 products
@@ -906,6 +908,7 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
       h->s8_groups = s8_groups(n);
       h->Hs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(n, S8_COLS_A)));
       h->Xs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(ne, S8_COLS_B)));
+      h->s8tail = static_cast<float*>(dev_alloc(h, s8_tail_bytes(h->cplx)));
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));

@@ -144,6 +144,34 @@ def test_filter_bf16x3_error_bound(pk, cplx, n, k):
     assert np.median(err) > 3e-7, np.median(err)
 
 
+@pytest.mark.parametrize("cplx", [True, False])
+def test_filter_bf16x3_whole_tiles_and_split_tail(pk, cplx):
+    """n=4100, k=2100: 17 x 17 tiles of 256 x 128, more than one round of
+    workgroups on the device, so a launch runs whole tiles and (when the
+    last round is at most half full) a split-K tail whose FP32 partial tiles
+    are summed afterwards; the active block shrinks with the degrees, so the
+    tile count changes from step to step.  Sampled columns (first and last
+    of column tiles, the ragged last tile) against the oracle's filter of
+    those columns (the filter acts on each column separately)."""
+    n, k = 4100, 2100
+    announce(f"filter bf16x3 whole tiles + split tail n={n} k={k} cplx={cplx}")
+    g = np.random.Generator(np.random.PCG64(4100 + cplx))
+    a = gen.gaussian(g, (n, n), cplx)
+    h = (a + a.conj().T) / (2.0 * np.sqrt(2.0 * n))  # semicircle on about [-1, 1]
+    del a
+    x = gen.gaussian(g, (n, k), cplx)
+    deg = np.sort(2 * g.integers(1, 6, size=k)).astype(np.int32)
+    b_sup, mu_1, mu_ne = 1.1, -1.1, -0.7
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_BF16X3)
+    assert mv == int(deg.sum())
+    cols = np.array([0, 1, 127, 128, 1000, 1791, 2047, 2048, 2099])
+    y_ref, _ = oracle.chebyshev_filter(h, x[:, cols], deg[cols], b_sup, mu_1, mu_ne)
+    y = to_np(y)[:, cols]
+    err = np.linalg.norm(y - y_ref, axis=0) / np.linalg.norm(y_ref, axis=0)
+    assert np.all(err < 1e-4), (err.max(), int(cols[err.argmax()]))
+    assert np.median(err) > 3e-7, np.median(err)
+
+
 def test_filter_bf16x3_closed_form_diagonal(pk):
     """H = diag(lambda): p(H) x = p(lambda) * x column by column."""
     announce("filter bf16x3 closed form on diag(lambda)")
