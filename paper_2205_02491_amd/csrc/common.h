@@ -86,6 +86,12 @@ struct GemmArgs {
   // PREC_BF16X3: workspace (s8_tail_bytes) for the split-K tail of the
   // launch; nullptr runs every tile whole
   float* s8_tail;
+  // Triangular structure (0: none).  SPLITK, square result: only the tiles
+  // on and above the diagonal are computed (Hermitian products; the
+  // reduction mirrors them).  STORE with B as stored: column j of B is zero
+  // below row tri_row0 + j, so a column tile's K loop stops there.
+  int tri;
+  int64_t tri_row0;
 };
 
 // ------------------------------------------------------------------ split BF16
@@ -122,7 +128,10 @@ void gemm(bool cplx, Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g,
 int gemm_row_tiles(int64_t M);
 // Split-K plan for an M x N result with long K: number of slices and the
 // per-slice K length; workspace elements needed = splits * M * N.
-void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice);
+void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice,
+                 bool tri = false);
+// Edge of the square tiles of the split-K products (the unit of `tri`).
+int splitk_tile();
 
 // ------------------------------------------------------------------ misc kernels
 void fill_zero(void* p, int64_t bytes, hipStream_t st);
@@ -130,9 +139,12 @@ void copy_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, 
                int64_t k, hipStream_t st);
 void gather_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd, int64_t n,
                  int64_t k, const int* perm_dev, hipStream_t st);
-// sum the split-K slices ws[z][i + j*M] into C (ld ldc); herm: C=(S+S^H)/2
+// sum the split-K slices ws[z][i + j*M] into C (ld ldc); herm: C=(S+S^H)/2.
+// tri_tile > 0 (herm, M == N): only the tiles of that edge on and above the
+// diagonal were computed; C = S above the diagonal tiles, its conjugate
+// transpose below them, (S+S^H)/2 within them.
 void splitk_reduce(bool cplx, const void* ws, int splits, int64_t M, int64_t N, void* C,
-                   int64_t ldc, bool herm, hipStream_t st);
+                   int64_t ldc, bool herm, hipStream_t st, int tri_tile = 0);
 // Gram post-processing for Cholesky QR: d_j = 1/sqrt(S_jj); S = D S D + shift*I;
 // flags[0] set to 1 if some S_jj <= 0 or is not finite.
 void gram_scale(bool cplx, void* S, int64_t lds, int64_t k, double shift, double* d,

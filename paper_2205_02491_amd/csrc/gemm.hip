@@ -151,13 +151,29 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   const int per_xcd = gridDim.x >> 3;
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= ntiles) return;
-  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  int tm = t / tiles_n, tn = t - tm * tiles_n;
+  if constexpr (EPI == EPI_SPLITK) {
+    static_assert(EPI != EPI_SPLITK || TBM == TBN, "square split-K tiles");
+    if (g.tri) {
+      // the tiles with tm <= tn, column by column: t = tn (tn + 1) / 2 + tm
+      int c = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      if ((c + 1) * (c + 2) / 2 <= t) ++c;
+      if (c * (c + 1) / 2 > t) --c;
+      tn = c;
+      tm = t - c * (c + 1) / 2;
+    }
+  }
   const int64_t m0 = (int64_t)tm * TBM, n0 = (int64_t)tn * TBN;
   const int64_t M = g.M, N = g.N;
   int64_t kbeg = 0, kend = g.K;
   if constexpr (EPI == EPI_SPLITK) {
     kbeg = (int64_t)blockIdx.z * g.kslice;
     kend = kbeg + g.kslice < g.K ? kbeg + g.kslice : g.K;
+  }
+  if constexpr (EPI == EPI_STORE && OPB == OP_N) {
+    // B upper triangular from row tri_row0: rows past tri_row0 + n0 + TBN
+    // of this column tile are zero
+    if (g.tri && g.tri_row0 + n0 + TBN < kend) kend = g.tri_row0 + n0 + TBN;
   }
 
   const int tid = threadIdx.x;
@@ -445,7 +461,11 @@ template <typename TA, typename TC, bool CPLX, int OPA, int OPB, int EPI, int BK
 void launch(const GemmArgs& g, hipStream_t st) {
   const int tiles_m = (int)((g.M + TBM - 1) / TBM);
   const int tiles_n = (int)((g.N + TBN - 1) / TBN);
-  const int ntiles = tiles_m * tiles_n;
+  int ntiles = tiles_m * tiles_n;
+  if (EPI == EPI_SPLITK && g.tri) {
+    CHASE_REQUIRE(g.M == g.N && TBM == TBN, "triangular split-K needs a square result");
+    ntiles = tiles_m * (tiles_m + 1) / 2;
+  }
   const int grid_x = (ntiles + 7) / 8 * 8;
   dim3 grid(grid_x, 1, EPI == EPI_SPLITK ? g.splits : 1);
   hipLaunchKernelGGL((gemm_kernel<TA, TC, CPLX, OPA, OPB, EPI, BKT, G3, TBM, TBN, WAVES_M, WAVES_N>),
@@ -499,9 +519,14 @@ void dispatch(Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g, hipStream_t
 }  // namespace
 
 int gemm_row_tiles(int64_t M) { return (int)((M + BM - 1) / BM); }
+int splitk_tile() { return BM; }
 
-void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice) {
-  const int64_t tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+// About 1024 workgroups: slices = ceil(1024 / tiles), each at least four K
+// chunks long.  tri: the tiles on and above the diagonal only.
+void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice, bool tri) {
+  static_assert(BM == BN, "square split-K tiles");
+  const int64_t tm = (M + BM - 1) / BM;
+  const int64_t tiles = tri ? tm * (tm + 1) / 2 : tm * ((N + BN - 1) / BN);
   int64_t s = (1024 + tiles - 1) / tiles;
   const int64_t smax = (K + 4 * BK_MIN - 1) / (4 * BK_MIN);  // >= 4 chunks per slice
   if (s > smax) s = smax;

@@ -49,18 +49,25 @@ __global__ void copy_cols_k(const double* __restrict__ src, int64_t lds, double*
 
 template <bool CPLX>
 __global__ void splitk_reduce_k(const double* __restrict__ ws, int splits, int64_t M, int64_t N,
-                                double* __restrict__ C, int64_t ldc, bool herm) {
+                                double* __restrict__ C, int64_t ldc, bool herm, int tri_tile) {
   const int64_t total = M * N;
   const int W = CPLX ? 2 : 1;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = e % M, j = e / M;
+    // triangular products (Hermitian, square): tiles below the diagonal were
+    // not computed; their entries are the conjugates of the mirrored ones
+    const bool mirror = tri_tile > 0 && i / tri_tile > j / tri_tile;
+    const bool diag = tri_tile > 0 && i / tri_tile == j / tri_tile;
+    const int64_t src = mirror ? j + i * M : e;
     double sr = 0, si = 0;
     for (int z = 0; z < splits; ++z) {
-      sr += ws[(z * total + e) * W];
-      if (CPLX) si += ws[(z * total + e) * W + 1];
+      sr += ws[(z * total + src) * W];
+      if (CPLX) si += ws[(z * total + src) * W + 1];
     }
-    if (herm) {
+    if (mirror) {
+      si = -si;
+    } else if (herm && (tri_tile == 0 || diag)) {
       // (S + S^H)/2 at (i, j): needs S(j, i) as well
       const int64_t et = j + i * M;
       double tr = 0, ti = 0;
@@ -631,16 +638,17 @@ void gather_cols(bool cplx, const void* src, int64_t lds, void* dst, int64_t ldd
 }
 
 void splitk_reduce(bool cplx, const void* ws, int splits, int64_t M, int64_t N, void* C,
-                   int64_t ldc, bool herm, hipStream_t st) {
+                   int64_t ldc, bool herm, hipStream_t st, int tri_tile) {
+  CHASE_REQUIRE(tri_tile == 0 || (herm && M == N), "triangular reduction of a non-Hermitian product");
   const int nb = blocks_for(M * N, TPB, 8192);
   if (cplx)
     hipLaunchKernelGGL(splitk_reduce_k<true>, dim3(nb), dim3(TPB), 0, st,
                        static_cast<const double*>(ws), splits, M, N, static_cast<double*>(C),
-                       ldc, herm);
+                       ldc, herm, tri_tile);
   else
     hipLaunchKernelGGL(splitk_reduce_k<false>, dim3(nb), dim3(TPB), 0, st,
                        static_cast<const double*>(ws), splits, M, N, static_cast<double*>(C),
-                       ldc, herm);
+                       ldc, herm, tri_tile);
   CHASE_HIP(hipGetLastError());
 }
 

@@ -103,8 +103,9 @@ size_t splitk_ws_elems(int ne) {
   for (int k = 1; k <= ne; ++k) {
     int s;
     int64_t ks;
-    // K is at least ne (the library's projections have K = n >= ne)
-    splitk_plan(k, k, INT64_MAX / 4, &s, &ks);
+    // K is at least ne (the library's projections have K = n >= ne); the
+    // Hermitian products computed as triangles have the most slices
+    splitk_plan(k, k, INT64_MAX / 4, &s, &ks, true);
     mx = std::max(mx, (size_t)s * k * k);
   }
   return mx;
@@ -166,23 +167,35 @@ GemmArgs gargs(int64_t M, int64_t N, int64_t K, const void* A, int64_t lda, cons
   return g;
 }
 
-// C (k1 x k2, ld ldc) = A^H B for tall A (K x k1), B (K x k2); herm: (S+S^H)/2
+// C (k1 x k2, ld ldc) = A^H B for tall A (K x k1), B (K x k2).  herm: the
+// product is Hermitian (k1 == k2); only the tiles on and above the diagonal
+// are computed and the result is made exactly Hermitian (mirrored tiles,
+// (S+S^H)/2 within the diagonal ones).
 void gram(chase_handle_s* h, const void* A, int64_t lda, const void* B, int64_t ldb, int64_t K,
           int64_t k1, int64_t k2, void* C, int64_t ldc, bool herm, hipStream_t st) {
+  const bool tri = herm && k1 == k2;
   int splits;
   int64_t ks;
-  splitk_plan(k1, k2, K, &splits, &ks);
+  splitk_plan(k1, k2, K, &splits, &ks, tri);
   CHASE_REQUIRE((size_t)splits * k1 * k2 <= h->ws_elems, "split-K workspace too small");
   GemmArgs g = gargs(k1, k2, K, A, lda, B, ldb, h->ws, k1);
   g.splits = splits;
   g.kslice = ks;
+  g.tri = tri ? 1 : 0;
   gemm(h->cplx, PREC_F64, OP_C, OP_N, EPI_SPLITK, g, st);
-  splitk_reduce(h->cplx, h->ws, splits, k1, k2, C, ldc, herm, st);
+  splitk_reduce(h->cplx, h->ws, splits, k1, k2, C, ldc, herm, st, tri ? splitk_tile() : 0);
 }
 
+// C = A B; tri_row0 >= 0: column j of B is zero below row tri_row0 + j
+// (an upper-triangular factor), which bounds the K loop of each column tile.
 void gemm_nn(chase_handle_s* h, int64_t M, int64_t N, int64_t K, const void* A, int64_t lda,
-             const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+             const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st,
+             int64_t tri_row0 = -1) {
   GemmArgs g = gargs(M, N, K, A, lda, B, ldb, C, ldc);
+  if (tri_row0 >= 0) {
+    g.tri = 1;
+    g.tri_row0 = tri_row0;
+  }
   gemm(h->cplx, PREC_F64, OP_N, OP_N, EPI_STORE, g, st);
 }
 
@@ -496,8 +509,9 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
                                 static_cast<double*>(R), ldr, h->d_info),
                "dtrtri");
     triu_rowscale(cplx, R, ldr, k, h->d_scale, st);
-    // Wb = X * (D R^{-1}); the locked columns keep their values
-    gemm_nn(h, n, k - L, k, X, ldx, off(R, (int64_t)L * ldr, h->esz), ldr, Wb, n, st);
+    // Wb = X * (D R^{-1}); the locked columns keep their values.  Column j
+    // of the factor's block [L, k) is zero below row L + j.
+    gemm_nn(h, n, k - L, k, X, ldx, off(R, (int64_t)L * ldr, h->esz), ldr, Wb, n, st, L);
     copy_cols(cplx, Wb, n, off(X, (int64_t)L * ldx, h->esz), ldx, n, k - L, st);
   }
 }
