@@ -294,7 +294,9 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
     __syncthreads();
     // 8 columns of H per round: 16 independent 16-byte loads in flight per
     // thread before the arithmetic that consumes them (16 columns or more
-    // workgroups measured no faster: 5.4 TB/s at n=20000, 4 vectors)
+    // workgroups measured no faster).  H is streamed once per step, far
+    // larger than the caches: nontemporal loads (the same column-block read
+    // pattern alone: 6.9 TB/s with them, 6.1 TB/s without, at n=20000).
     constexpr int CU = 8;
     int c = 0;
     for (; c + CU <= ncs; c += CU) {
@@ -309,11 +311,11 @@ __global__ __launch_bounds__(TPB) void lz_gemv_k(const double* __restrict__ H, i
           hi[u][r] = 0.0;
           if (i < n) {
             if (CPLX) {
-              const d2v h = *reinterpret_cast<const d2v*>(hc + 2 * i);
+              const d2v h = __builtin_nontemporal_load(reinterpret_cast<const d2v*>(hc + 2 * i));
               hr[u][r] = h.x;
               hi[u][r] = h.y;
             } else {
-              hr[u][r] = hc[i];
+              hr[u][r] = __builtin_nontemporal_load(hc + i);
             }
           }
         }
@@ -589,9 +591,13 @@ __global__ void sym_divdiff_k(const double* __restrict__ M, int64_t ldm,
 
 constexpr int LZ_VEC_BLOCKS = 128;
 
+// Column splits of the block GEMV: about 512 workgroups, two per CU of the
+// 256-CU MI355X, all resident at once (each streams a long range of
+// columns).  Measured at n=20000 with nontemporal loads: 6.7-6.9 TB/s with
+// 480 workgroups, 5.9 TB/s with ~2048 (two rounds of resident workgroups).
 int lz_splits(int64_t n) {
   const int64_t row_blocks = (n + LZ_ROWS - 1) / LZ_ROWS;
-  int64_t s = (2048 + row_blocks - 1) / row_blocks;  // ~2048 workgroups
+  int64_t s = 512 / row_blocks;
   const int64_t smax = (n + 63) / 64;
   if (s > smax) s = smax;
   if (s > 64) s = 64;
