@@ -332,47 +332,36 @@ __device__ inline unsigned bf16_bits(float f) {
 }
 __device__ inline double bf16_value(unsigned b) { return (double)__uint_as_float(b << 16); }
 
+// One thread per row of a column (consecutive threads read consecutive
+// rows: coalesced), writing its hi and lo halves as 2-byte values into the
+// planes of its 8-row group.
 template <bool CPLX>
 __global__ void split_s8_k(const double* __restrict__ src, int64_t lds, int64_t rows,
                            int64_t cols, int64_t cols_pad, int64_t groups, int conj,
                            char* __restrict__ dst) {
   constexpr int P = CPLX ? 4 : 2;
-  const int64_t total = cols_pad * groups;
+  const int64_t rows_pad = groups * 8;
+  const int64_t total = cols_pad * rows_pad;
   for (int64_t idx = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t c = idx / groups, gr = idx - c * groups;
-    unsigned hi[P / 2][8], lo[P / 2][8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int64_t r = gr * 8 + e;
-      double x[2] = {0.0, 0.0};
-      if (c < cols && r < rows) {
-        if constexpr (CPLX) {
-          const d2v v = *reinterpret_cast<const d2v*>(src + 2 * (r + c * lds));
-          x[0] = v.x;
-          x[1] = conj ? -v.y : v.y;
-        } else {
-          x[0] = src[r + c * lds];
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < P / 2; ++q) {
-        const unsigned bh = bf16_bits((float)x[q]);
-        hi[q][e] = bh;
-        lo[q][e] = bf16_bits((float)(x[q] - bf16_value(bh)));
+    const int64_t c = idx / rows_pad, r = idx - c * rows_pad;
+    double x[2] = {0.0, 0.0};
+    if (c < cols && r < rows) {
+      if constexpr (CPLX) {
+        const d2v v = *reinterpret_cast<const d2v*>(src + 2 * (r + c * lds));
+        x[0] = v.x;
+        x[1] = conj ? -v.y : v.y;
+      } else {
+        x[0] = src[r + c * lds];
       }
     }
-    u4v* out = reinterpret_cast<u4v*>(dst + idx * P * 16);
+    unsigned short* out =
+        reinterpret_cast<unsigned short*>(dst + (c * groups + (r >> 3)) * P * 16) + (r & 7);
 #pragma unroll
     for (int q = 0; q < P / 2; ++q) {
-      u4v vh, vl;
-#pragma unroll
-      for (int w = 0; w < 4; ++w) {
-        vh[w] = hi[q][2 * w] | (hi[q][2 * w + 1] << 16);
-        vl[w] = lo[q][2 * w] | (lo[q][2 * w + 1] << 16);
-      }
-      out[2 * q] = vh;
-      out[2 * q + 1] = vl;
+      const unsigned bh = bf16_bits((float)x[q]);
+      out[(2 * q) * 8] = (unsigned short)bh;
+      out[(2 * q + 1) * 8] = (unsigned short)bf16_bits((float)(x[q] - bf16_value(bh)));
     }
   }
 }
@@ -383,7 +372,7 @@ void split_s8(bool cplx, bool conj, const void* src, int64_t lds, int64_t rows, 
               int64_t cols_pad, void* dst, int64_t groups, hipStream_t st) {
   CHASE_REQUIRE(groups * 8 >= rows && groups % (S8_KPAD / 8) == 0 && cols_pad >= cols,
                 "split layout too small");
-  const int64_t total = cols_pad * groups;
+  const int64_t total = cols_pad * groups * 8;
   if (total <= 0) return;
   const int64_t blocks = std::min<int64_t>((total + 255) / 256, 65536);
   if (cplx)
