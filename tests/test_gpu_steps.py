@@ -242,13 +242,18 @@ def test_lanczos_matches_oracle(pk, cplx):
 
 
 # ------------------------------------------------------------------ QR
-@pytest.mark.parametrize("locked", [0, 7])
-def test_qr_invariants_and_span(pk, locked):
-    announce(f"qr locked={locked}")
-    n, k = 1100, 150
-    g = np.random.Generator(np.random.PCG64(41))
-    y = gen.haar(n, g, True)[:, :locked] if locked else np.zeros((n, 0), complex)
-    base = gen.gaussian(g, (n, k - locked), True)
+@pytest.mark.parametrize("n,k,locked,cplx", [(1100, 150, 0, True), (1100, 150, 7, True),
+                                             (1500, 400, 130, True), (1500, 400, 130, False)])
+def test_qr_invariants_and_span(pk, n, k, locked, cplx):
+    """k spans several 128-wide tiles: the Gram matrix is computed as the
+    tiles on and above the diagonal and mirrored, and X R^-1 stops at the
+    triangular factor's diagonal, offset by the locked columns (here also
+    more than a tile)."""
+    announce(f"qr n={n} k={k} locked={locked} cplx={cplx}")
+    g = np.random.Generator(np.random.PCG64(41 + k + cplx))
+    dt = complex if cplx else float
+    y = gen.haar(n, g, cplx)[:, :locked] if locked else np.zeros((n, 0), dt)
+    base = gen.gaussian(g, (n, k - locked), cplx)
     # columns with widely different scales and a near-dependency
     v = base * np.logspace(0, 6, k - locked)[None, :]
     v[:, 1] = v[:, 0] * 1e-3 + 1e-9 * base[:, 1]
@@ -263,11 +268,11 @@ def test_qr_invariants_and_span(pk, locked):
 
 
 # ------------------------------------------------------------------ RR + residual
-@pytest.mark.parametrize("cplx", [True, False])
-def test_rayleigh_ritz_matches_oracle(pk, cplx):
-    announce(f"rayleigh-ritz cplx={cplx}")
-    n, k = 1000, 140
-    h, lam, q, g = _problem(n, cplx, 51 + cplx)
+@pytest.mark.parametrize("cplx,k", [(True, 140), (False, 140), (True, 300)])
+def test_rayleigh_ritz_matches_oracle(pk, cplx, k):
+    announce(f"rayleigh-ritz cplx={cplx} k={k}")
+    n = 1000
+    h, lam, q, g = _problem(n, cplx, 51 + cplx + k)
     qa, _ = np.linalg.qr(gen.gaussian(g, (n, k), cplx) + q[:, :k] * 5)
     th_ref, va_ref = oracle.rayleigh_ritz(h, qa)
     r_ref = oracle.residual_norms(h, va_ref, th_ref, 1.3)
