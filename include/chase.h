@@ -77,7 +77,8 @@ typedef struct chase_opts {
   int lanczos_vecs;    /* number of Lanczos runs, 1..8 (default 4)           */
   int max_iter;        /* subspace iterations before NOCONV (default 50)     */
   int filter_prec;     /* chase_prec (default CHASE_PREC_FP64)                */
-  double switch_tol;   /* FP32->FP64 switch residual; <= 0: never           */
+  double switch_tol;   /* residual below which a vector leaves the low-
+                          precision filter for FP64; <= 0: never             */
   int verbose;         /* 1: one line per iteration on stderr                */
   int initial_rr;      /* 1: Rayleigh-Ritz on the start block before the first
                           filter (warm starts from approximate eigenvectors:
