@@ -123,9 +123,10 @@ size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex,
  * CHASE_ERR_NOMEM if the workspace exceeds the free device memory.  With
  * CHASE_PREC_FP32 the workspace includes a complex64 copy of H when it fits
  * (chase_workspace_bytes counts it); otherwise H is rounded on the fly.
- * With CHASE_PREC_BF16X3 the split copies of H and of the block (and
- * 64 MiB, 32 MiB real, of partial tiles for the product's split-K tail) are
- * required (NOMEM if they do not fit). */
+ * With CHASE_PREC_BF16X3 the split copy of H, two split copies of the
+ * block (a filter step's operand and the next step's, which the step writes
+ * beside its FP64 result) and 64 MiB (32 MiB real) of partial tiles for the
+ * product's split-K tail are required (NOMEM if they do not fit). */
 chase_status chase_create(chase_handle_t* handle, chase_dtype dtype, int64_t n,
                           int nev, int nex, const chase_opts* opts);
 void chase_destroy(chase_handle_t handle);

@@ -86,6 +86,12 @@ struct GemmArgs {
   // PREC_BF16X3: workspace (s8_tail_bytes) for the split-K tail of the
   // launch; nullptr runs every tile whole
   float* s8_tail;
+  // PREC_BF16X3, optional: the epilogue also writes the s8 split of its
+  // output (the next filter step's operand) to s8_next, output column j
+  // (>= s8_next_col0) as split column j - s8_next_col0, rows < M only (the
+  // zero padding rows of s8_next are left as they are)
+  void* s8_next;
+  int64_t s8_next_col0;
   // Triangular structure (0: none).  SPLITK, square result: only the tiles
   // on and above the diagonal are computed (Hermitian products; the
   // reduction mirrors them).  STORE with B as stored: column j of B is zero

@@ -35,6 +35,11 @@
 // all 64 banks.  Workgroup ids are remapped so that each of the 8 XCDs works
 // on a contiguous range of tiles (the same few row panels of H).
 //
+// The Chebyshev-step epilogue (FP64) can also write the split of its
+// output, the next filter step's operand, into a second s8 buffer with
+// 2-byte stores, so a filter call splits its block once instead of once per
+// step.
+//
 // One workgroup fits a CU (98 KB of LDS), so a launch runs in rounds of one
 // tile per CU and a last round that is at most half full would leave most
 // of the chip idle.  Those tiles are run as a split-K tail instead: each in
@@ -76,8 +81,40 @@ __device__ inline f16v mfma(u4v a, u4v b, f16v c) {
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
 }
 
+// Round-to-nearest-even float -> bf16 (finite inputs; NaN stays NaN).
+__device__ inline unsigned bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+__device__ inline double bf16_value(unsigned b) { return (double)__uint_as_float(b << 16); }
+
+// hi and lo halves of x (value), as 2-byte stores into plane q of the 8-row
+// group holding row r: out points at the row's slot in the group's first
+// plane (planes 16 bytes apart: hi of component q at plane 2q, lo at 2q+1).
+__device__ inline void put_split(unsigned short* out, int q, double x) {
+  const unsigned bh = bf16_bits((float)x);
+  out[(2 * q) * 8] = (unsigned short)bh;
+  out[(2 * q + 1) * 8] = (unsigned short)bf16_bits((float)(x - bf16_value(bh)));
+}
+
+// The split of output element (i, j) into the next step's operand.
+template <bool CPLX>
+__device__ inline void emit_next_split(const GemmArgs& g, int64_t i, int64_t j, double vr,
+                                       double vi) {
+  constexpr int P = CPLX ? 4 : 2;
+  if (!g.s8_next || j < g.s8_next_col0) return;
+  unsigned short* out = reinterpret_cast<unsigned short*>(
+                            static_cast<char*>(g.s8_next) +
+                            ((j - g.s8_next_col0) * g.s8_groups + (i >> 3)) * P * 16) +
+                        (i & 7);
+  put_split(out, 0, vr);
+  if constexpr (CPLX) put_split(out, 1, vi);
+}
+
 // Chebyshev-step update of one element (FP64): out = alpha (acc - gamma X)
-// + beta out [+ colcoef_j F].
+// + beta out [+ colcoef_j F]; with s8_next set, also its split.
 template <bool CPLX>
 __device__ inline void cheb_elem(const GemmArgs& g, int64_t i, int64_t j, double vr, double vi) {
   double* __restrict__ Cd = static_cast<double*>(g.C);
@@ -106,6 +143,7 @@ __device__ inline void cheb_elem(const GemmArgs& g, int64_t i, int64_t j, double
     if (g.colcoef) vr += g.colcoef[j] * Fd[i + j * g.ldf];
     Cd[o] = vr;
   }
+  emit_next_split<CPLX>(g, i, j, vr, vi);
 }
 
 // Epilogue of a whole tile.  Accumulator r of fragment (fi, fj) in lane
@@ -323,14 +361,6 @@ __global__ void tail_finish_k(GemmArgs g, int tiles_n, TailPlan tp) {
 }
 
 // ------------------------------------------------------------------ split
-// Round-to-nearest-even float -> bf16 (finite inputs; NaN stays NaN).
-__device__ inline unsigned bf16_bits(float f) {
-  unsigned u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);
-  u += 0x7fffu + ((u >> 16) & 1u);
-  return u >> 16;
-}
-__device__ inline double bf16_value(unsigned b) { return (double)__uint_as_float(b << 16); }
 
 // One thread per row of a column (consecutive threads read consecutive
 // rows: coalesced), writing its hi and lo halves as 2-byte values into the
@@ -358,11 +388,7 @@ __global__ void split_s8_k(const double* __restrict__ src, int64_t lds, int64_t 
     unsigned short* out =
         reinterpret_cast<unsigned short*>(dst + (c * groups + (r >> 3)) * P * 16) + (r & 7);
 #pragma unroll
-    for (int q = 0; q < P / 2; ++q) {
-      const unsigned bh = bf16_bits((float)x[q]);
-      out[(2 * q) * 8] = (unsigned short)bh;
-      out[(2 * q + 1) * 8] = (unsigned short)bf16_bits((float)(x[q] - bf16_value(bh)));
-    }
+    for (int q = 0; q < P / 2; ++q) put_split(out, q, x[q]);
   }
 }
 

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -46,6 +47,7 @@ struct chase_handle_s {
   // and of the block being multiplied (ne padded to S8_COLS_B columns)
   void* Hs8 = nullptr;
   void* Xs8 = nullptr;
+  void* Xs8b = nullptr;     // second block split: step s writes step s+1's operand
   float* s8tail = nullptr;  // FP32 partial tiles of the GEMM's split-K tail
   int64_t s8_groups = 0;
   void* Rres = nullptr;  // residual vectors H v - theta v of the active block (mixed modes)
@@ -131,8 +133,9 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
   if (o.filter_prec == CHASE_PREC_FP32)
     s.h32 = (size_t)n * n * esz / 2 + (size_t)n * ne * esz;
   else if (o.filter_prec == CHASE_PREC_BF16X3)
-    s.h32 = s8_bytes(cplx, n, s8_pad(n, S8_COLS_A)) + s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) +
-            s8_tail_bytes(cplx) + (size_t)n * ne * esz;
+    s.h32 = s8_bytes(cplx, n, s8_pad(n, S8_COLS_A)) +
+            2 * s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) + s8_tail_bytes(cplx) +
+            (size_t)n * ne * esz;
   s.small += (size_t)(kMaxDegree + 1) * ne * 8;
   s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
   return s;
@@ -210,19 +213,43 @@ Prec to_prec(int p) {
   return p == CHASE_PREC_BF16X3 ? PREC_BF16X3 : p == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64;
 }
 
-// Split-BF16 operands of one filter step: the block B (n x cols, ld ldb) of
-// g is split into the handle's block buffer; the split of H is the handle's.
-// The split runs outside the timed GEMM window: it is one pass over the
-// block (HBM-bound), the GEMM reads it n/256 times.
-void bf16_operands(chase_handle_s* h, GemmArgs& g, int cols, hipStream_t st) {
-  CHASE_REQUIRE(h->Hs8 && h->Xs8, "split-BF16 products need a handle created with "
-                                  "filter_prec = CHASE_PREC_BF16X3");
-  split_s8(h->cplx, false, g.B, g.ldb, h->n, cols, s8_pad(cols, S8_COLS_B), h->Xs8, h->s8_groups,
-           st);
-  g.a_s8 = h->Hs8;
-  g.b_s8 = h->Xs8;
-  g.s8_groups = h->s8_groups;
-  g.s8_tail = h->s8tail;
+// Split-BF16 operands of the filter steps.  The split of H is the
+// handle's.  The block operand of a step is split by the split kernel on the
+// first step of a filter call; every later step finds it already written by
+// the previous step's epilogue (which emits the split of its output beside
+// the FP64 result), so the block is split once per call, not per step.
+// The split kernel runs outside the timed GEMM window.
+struct Bf16Steps {
+  chase_handle_s* h;
+  void* cur;          // split of this step's operand
+  void* other;        // where this step's epilogue writes the next operand
+  bool ready = false; // cur already holds this step's operand
+  explicit Bf16Steps(chase_handle_s* hh) : h(hh), cur(hh->Xs8), other(hh->Xs8b) {
+    CHASE_REQUIRE(h->Hs8 && h->Xs8 && h->Xs8b, "split-BF16 products need a handle created with "
+                                              "filter_prec = CHASE_PREC_BF16X3");
+  }
+  // g: the step's GEMM (B = its FP64 operand, cols columns); next_col0 >= 0:
+  // the next step multiplies this step's output columns [next_col0, cols)
+  void prepare(GemmArgs& g, int cols, int next_col0, hipStream_t st) {
+    if (!ready)
+      split_s8(h->cplx, false, g.B, g.ldb, h->n, cols, s8_pad(cols, S8_COLS_B), cur,
+               h->s8_groups, st);
+    g.a_s8 = h->Hs8;
+    g.b_s8 = cur;
+    g.s8_groups = h->s8_groups;
+    g.s8_tail = h->s8tail;
+    g.s8_next = next_col0 >= 0 ? other : nullptr;
+    g.s8_next_col0 = next_col0 >= 0 ? next_col0 : 0;
+  }
+  void advance(const GemmArgs& g) {
+    ready = g.s8_next != nullptr;
+    if (ready) std::swap(cur, other);
+  }
+};
+
+// First active column of filter step s (degrees non-decreasing).
+int step_first_col(const int* deg, int k, int s) {
+  return (int)(std::lower_bound(deg, deg + k, s) - deg);
 }
 
 // split of conj(H) = H^T (H Hermitian) for the split-BF16 products
@@ -260,8 +287,10 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     CHASE_HIP(hipEventCreate(&e));
     h->evs.push_back(e);
   }
+  std::unique_ptr<Bf16Steps> bsteps;
+  if (prec == PREC_BF16X3) bsteps.reset(new Bf16Steps(h));
   for (int s = 1; s <= mmax; ++s) {
-    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    const int a0 = step_first_col(deg, k, s);
     const int cols = k - a0;
     if (cols <= 0) continue;
     void* src = (s & 1) ? X : Wb;  // X_{s-1}
@@ -273,10 +302,14 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     g.gamma = cf[s - 1].gamma;
     g.beta = cf[s - 1].beta;
     g.a_f32 = a_f32;
-    if (prec == PREC_BF16X3) bf16_operands(h, g, cols, st);
+    if (bsteps) {
+      const int a1 = step_first_col(deg, k, s + 1);
+      bsteps->prepare(g, cols, (s < mmax && a1 < k) ? a1 - a0 : -1, st);
+    }
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
     gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
+    if (bsteps) bsteps->advance(g);
     ft.matvecs += cols;
     ft.launches += 1;
     if (tape)
@@ -347,8 +380,10 @@ void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, i
   // D_1 = alpha_1 r ; D_0 = 0
   axpby_cols(h->cplx, h->d_coef + k, R, ldr, nullptr, W1, n, n, k, st);
   fill_zero(W2, (int64_t)n * k * (int64_t)h->esz, st);
+  std::unique_ptr<Bf16Steps> bsteps;
+  if (prec == PREC_BF16X3) bsteps.reset(new Bf16Steps(h));
   for (int s = 2; s <= mmax; ++s) {
-    const int a0 = (int)(std::lower_bound(deg, deg + k, s) - deg);
+    const int a0 = step_first_col(deg, k, s);
     const int cols = k - a0;
     if (cols <= 0) continue;
     void* src = (s & 1) ? W2 : W1;  // D_{s-1}
@@ -362,10 +397,14 @@ void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, i
     g.colcoef = h->d_coef + (size_t)s * k + a0;
     g.F = const_cast<char*>(static_cast<const char*>(R)) + (int64_t)a0 * ldr * (int64_t)h->esz;
     g.ldf = ldr;
-    if (prec == PREC_BF16X3) bf16_operands(h, g, cols, st);
+    if (bsteps) {
+      const int a1 = step_first_col(deg, k, s + 1);
+      bsteps->prepare(g, cols, (s < mmax && a1 < k) ? a1 - a0 : -1, st);
+    }
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
     gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
+    if (bsteps) bsteps->advance(g);
     ft.matvecs += cols;
     ft.launches += 1;
   }
@@ -921,7 +960,13 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     } else if (o.filter_prec == CHASE_PREC_BF16X3) {
       h->s8_groups = s8_groups(n);
       h->Hs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(n, S8_COLS_A)));
-      h->Xs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(ne, S8_COLS_B)));
+      const size_t xb = s8_bytes(h->cplx, n, s8_pad(ne, S8_COLS_B));
+      h->Xs8 = dev_alloc(h, xb);
+      h->Xs8b = dev_alloc(h, xb);
+      // the zero padding rows of both block splits: the split kernel rewrites
+      // them, the epilogue that fills the second buffer never touches them
+      CHASE_HIP(hipMemset(h->Xs8, 0, xb));
+      CHASE_HIP(hipMemset(h->Xs8b, 0, xb));
       h->s8tail = static_cast<float*>(dev_alloc(h, s8_tail_bytes(h->cplx)));
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }

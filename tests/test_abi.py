@@ -60,14 +60,15 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
     o = pk.default_opts(filter_prec=1)
     assert pk.chase_workspace_bytes(20000, 1000, 300, opts=o) >= 20000 ** 2 * 8
     # split-BF16 mode adds the split of H (rows padded to 16, columns to 256,
-    # 4 bf16 per complex entry), the split of the block (columns padded to
-    # 128), 256 FP32 partial tiles of 256 x 128 (re and im) for the GEMM's
-    # split-K tail and the residual block
+    # 4 bf16 per complex entry), two splits of the block (columns padded to
+    # 128: a step's operand and the next step's, written by its epilogue),
+    # 256 FP32 partial tiles of 256 x 128 (re and im) for the GEMM's split-K
+    # tail and the residual block
     for n, nev, nex, cplx in [(30000, 1500, 500, True), (1000, 100, 40, False)]:
         ne, esz = nev + nex, (16 if cplx else 8)
         rows = -(-n // 16) * 16
         per = 8 if cplx else 4
-        extra = rows * per * (-(-n // 256) * 256) + rows * per * (-(-ne // 128) * 128) \
+        extra = rows * per * (-(-n // 256) * 256) + 2 * rows * per * (-(-ne // 128) * 128) \
             + 256 * 256 * 128 * (2 if cplx else 1) * 4 + n * ne * esz
         o3 = pk.default_opts(filter_prec=pk.PREC_BF16X3)
         b3 = pk.chase_workspace_bytes(n, nev, nex, cplx=cplx, opts=o3)
