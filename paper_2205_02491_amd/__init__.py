@@ -147,6 +147,10 @@ def _stream():
 
 
 def _dev(t):
+    if t.is_conj() or t.is_neg():
+        # a lazy conjugate/negative view: its memory holds the other values
+        raise ValueError("tensor is a lazy conjugate or negative view; call "
+                         "resolve_conj() / resolve_neg() first")
     if not t.is_cuda:
         raise ValueError("tensor must be on the GPU")
     return ctypes.c_void_p(t.data_ptr())
@@ -154,8 +158,11 @@ def _dev(t):
 
 def _colmajor(x):
     """Column-major buffer (as a row-major (k, n) tensor) of the vectors of x
-    (n, k) in the conj(H) frame: x.mH, contiguous."""
-    return x.mH.contiguous()
+    (n, k) in the conj(H) frame: x.mH materialised in new memory.  (For a
+    single vector x.mH is already contiguous, and .contiguous() would return
+    the lazy conjugate view of x's own memory.)"""
+    import torch
+    return x.mH.resolve_conj().clone(memory_format=torch.contiguous_format)
 
 
 class Handle:

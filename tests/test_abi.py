@@ -109,3 +109,21 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(pk, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         pk.lib()
+
+
+def test_colmajor_buffers_are_materialised_copies():
+    """The binding hands the library x.mH in new memory.  For a single
+    vector x.mH is already contiguous: without materialising, the library
+    would read x's unconjugated memory through a lazy conjugate view and
+    write into the caller's tensor."""
+    import torch
+    pk = _lib()
+    for shape in [(5, 1), (5, 3), (1, 1)]:
+        for dt in (torch.complex128, torch.float64):
+            x = torch.randn(shape, dtype=dt)
+            b = pk._colmajor(x)
+            assert not b.is_conj() and b.is_contiguous()
+            assert b.data_ptr() != x.data_ptr()
+            assert torch.equal(b, x.conj().T.resolve_conj())
+    with pytest.raises(ValueError, match="lazy conjugate"):
+        pk._dev(torch.randn(3, dtype=torch.complex128).conj())

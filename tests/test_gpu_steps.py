@@ -172,6 +172,25 @@ def test_filter_bf16x3_whole_tiles_and_split_tail(pk, cplx):
     assert np.median(err) > 3e-7, np.median(err)
 
 
+@pytest.mark.parametrize("n,k", [(17, 1), (256, 128), (257, 129), (300, 2)])
+def test_filter_bf16x3_edge_shapes(pk, n, k):
+    """Split-BF16 filter at edge shapes: a single column, exact tile
+    multiples, one past them (ragged tails in rows, columns and K), and
+    degrees that drop all but the last column after the first steps (the
+    next-step split then covers one column)."""
+    announce(f"filter bf16x3 edge n={n} k={k}")
+    h, lam, q, g = _problem(n, True, 5100 + n + k)
+    x = gen.gaussian(g, (n, k), True)
+    deg = np.full(k, 2, dtype=np.int32)
+    deg[-1] = 8
+    b_sup, mu_1, mu_ne = 1.02, -1.0, -0.6
+    y_ref, mv_ref = oracle.chebyshev_filter(h, x, deg, b_sup, mu_1, mu_ne)
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_BF16X3)
+    assert mv == mv_ref
+    err = np.linalg.norm(to_np(y) - y_ref, axis=0) / np.linalg.norm(y_ref, axis=0)
+    assert np.all(err < 1e-4), (err.max(), int(err.argmax()))
+
+
 def test_filter_bf16x3_closed_form_diagonal(pk):
     """H = diag(lambda): p(H) x = p(lambda) * x column by column."""
     announce("filter bf16x3 closed form on diag(lambda)")
