@@ -241,12 +241,12 @@ def test_bf16x3_needs_split_handle(pk):
 
 
 # ------------------------------------------------------------------ Lanczos
-@pytest.mark.parametrize("cplx", [True, False])
-def test_lanczos_matches_oracle(pk, cplx):
-    announce(f"lanczos parity cplx={cplx}")
+@pytest.mark.parametrize("cplx,nvec", [(True, 4), (False, 4), (True, 1)])
+def test_lanczos_matches_oracle(pk, cplx, nvec):
+    announce(f"lanczos parity cplx={cplx} nvec={nvec}")
     n = 900
     h, lam, q, g = _problem(n, cplx, 31 + cplx)
-    s = gen.gaussian(g, (n, 4), cplx)
+    s = gen.gaussian(g, (n, nvec), cplx)
     runs = oracle.lanczos_runs(h, s, 25)
     b_ref, m1_ref, mne_ref, _ = oracle.spectral_bounds(h, s, 25, 120)
     handle = pk.Handle(n, 80, 40, to_gpu(h).dtype)
@@ -284,6 +284,32 @@ def test_qr_invariants_and_span(pk, n, k, locked, cplx):
     # same span: projector difference
     pdiff = qd @ qd.conj().T - q_ref @ q_ref.conj().T
     assert np.linalg.norm(pdiff, 2) < 1e-8
+
+
+def test_single_vector_entry_points(pk):
+    """One complex vector through QR, Rayleigh-Ritz and the eigenvalue
+    adjoint: a single column is the case where a torch view of the caller's
+    memory could reach the library unconjugated."""
+    announce("single-vector QR / Rayleigh-Ritz / eigenvalue adjoint")
+    import torch
+    n = 200
+    h, lam, q, g = _problem(n, True, 61)
+    x = gen.gaussian(g, (n, 1), True)
+    x_keep = x.copy()
+    xt = to_gpu(x)
+    qd = to_np(pk.chase_qr(xt))
+    assert np.array_equal(to_np(xt), x_keep)          # the input is not modified
+    ref = x / np.linalg.norm(x)
+    ph = np.vdot(ref[:, 0], qd[:, 0])                 # same vector up to a phase
+    assert abs(abs(ph) - 1.0) < 1e-12
+    th, v, res = pk.chase_rayleigh_ritz(to_gpu(h), to_gpu(ref), 1.0)
+    theta = float(np.real(np.vdot(ref[:, 0], h @ ref[:, 0])))
+    assert abs(th[0] - theta) < 1e-13
+    r = np.linalg.norm(h @ ref[:, 0] - theta * ref[:, 0])
+    assert abs(res[0] - r) < 1e-12 * max(1.0, r)
+    dH = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    pk.chase_eigval_adjoint(to_gpu(q[:, :1]), np.array([0.5]), dH)
+    np.testing.assert_allclose(to_np(dH), 0.5 * np.outer(q[:, 0], q[:, 0].conj()), atol=1e-14)
 
 
 # ------------------------------------------------------------------ RR + residual
