@@ -107,6 +107,28 @@ def test_solve_tiny_edge(pk):
     assert abs(ev[0] - w[0]) < 1e-10 * np.max(np.abs(w))
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("cplx", [True, False])
+def test_solve_tiny_edge_mixed(pk, prec, cplx):
+    """Smallest legal sizes with low-precision filter products: n=3 and n=17
+    (less than one 16-row group of the split layout past a multiple of 16),
+    nev=1, nex=1; the FP64 residual bar still holds."""
+    code = {"fp32": pk.PREC_FP32, "bf16x3": pk.PREC_BF16X3}[prec]
+    for n in (3, 17):
+        announce(f"solve tiny mixed n={n} prec={prec} cplx={cplx}")
+        g = np.random.Generator(np.random.PCG64(300 + n + cplx))
+        a = gen.gaussian(g, (n, n), cplx)
+        h = (a + a.conj().T) / 2
+        v0 = gen.gaussian(g, (n, 2), cplx)
+        s = gen.gaussian(g, (n, 4), cplx)
+        o = pk.default_opts(filter_prec=code)
+        ev, vec, res, st = pk.chase_solve(to_gpu(h), 1, 1, 1e-10, 4, to_gpu(v0), to_gpu(s), opts=o)
+        w = np.linalg.eigvalsh(h)
+        assert st["converged"]
+        assert abs(ev[0] - w[0]) < 1e-10 * np.max(np.abs(w))
+        assert res[0] <= 1e-10
+
+
 def test_solve_noconv_returns_partial(pk):
     announce("solve noconv")
     p = gen.make_uniform(n=300, nev=20, nex=10, cfg=13)
