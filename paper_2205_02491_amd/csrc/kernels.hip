@@ -380,7 +380,7 @@ __device__ inline void block_sum_store(double* vals, int nv, double* out) {
     if (lane == 0) red[wave][v] = x;
   }
   __syncthreads();
-  if (threadIdx.x < nv) {
+  if ((int)threadIdx.x < nv) {
     double s = 0;
     for (int w = 0; w < TPB / 64; ++w) s += red[w][threadIdx.x];
     out[(int64_t)blockIdx.x * nv + threadIdx.x] = s;
@@ -438,7 +438,7 @@ __global__ __launch_bounds__(TPB) void lz_orth_k(const double* __restrict__ dotp
       for (int b = 0; b < nblk; ++b) s += dotp[(int64_t)b * nv + v];
       alpha[v] = s;
     }
-    if (blockIdx.x == 0 && threadIdx.x < nv) alpha_out[threadIdx.x] = alpha[threadIdx.x];
+    if (blockIdx.x == 0 && (int)threadIdx.x < nv) alpha_out[threadIdx.x] = alpha[threadIdx.x];
   }
   for (int64_t i = blockIdx.x * (int64_t)TPB + threadIdx.x; i < n; i += (int64_t)gridDim.x * TPB) {
     for (int v = 0; v < nv; ++v) {
