@@ -248,6 +248,40 @@ chase_status chase_filter_adjoint(chase_handle_t handle, const void* H_dev,
                                   void* dH_dev, int64_t ldd, void* gX_dev,
                                   void* stream);
 
+/* Host-side steps of Algorithm 1 (no handle, no GPU): the scalar logic the
+ * solver applies between its device steps, for callers that drive the steps
+ * themselves (chase_lanczos, chase_filter, chase_qr, chase_rayleigh_ritz).
+ *
+ * chase_filter_coefficients: the m steps of the scaled Chebyshev recurrence
+ * of Eq. (3) (normalised at mu_1, damping [mu_ne, b_sup]) used by
+ * chase_filter: coef_host[3s], [3s+1], [3s+2] = alpha, gamma, beta of step
+ * s+1, X_{s+1} = alpha (H - gamma I) X_s + beta X_{s-1}.  Requires 1 <= m
+ * <= 1000 and mu_1 < mu_ne < b_sup.
+ *
+ * chase_spectral_bounds: b_sup (largest Ritz value of a run plus its last
+ * |beta|, maximised over runs), mu_1 (smallest Ritz value) and mu_ne (the
+ * density-of-states estimate of the n_e-th eigenvalue, clamped into
+ * [mu_1, b_sup]) from Lanczos tridiagonals in the layout chase_lanczos
+ * returns (alpha_host, beta_host: nvec x steps, run-major; a run ends at its
+ * first beta <= 1e-14 max|alpha|).  steps_host[nvec] (may be NULL) receives
+ * each run's length.  Requires 1 <= n_e <= n, beta >= 0.
+ *
+ * chase_degrees: the degree step of Algorithm 1 for k vectors with
+ * residuals resid_host[k] (> 0, the solver's normalisation) and Ritz values
+ * ritz_host[k]: with c = (b_sup + mu_ne)/2, e = (b_sup - mu_ne)/2,
+ * t = (ritz - c)/e and rho = max|t +- sqrt(t^2 - 1)|, degrees_host[a] =
+ * ceil(|ln(resid/tol)| / ln rho) + deg_extra, capped at max_deg (max_deg if
+ * rho <= 1 + 1e-12), at least 2, rounded up to even; with optimize_degree 0
+ * every degree is `degree` rounded up to even.  opts may be NULL. */
+chase_status chase_filter_coefficients(int m, double b_sup, double mu_1, double mu_ne,
+                                       double* coef_host);
+chase_status chase_spectral_bounds(const double* alpha_host, const double* beta_host, int nvec,
+                                   int steps, int64_t n, int n_e, double* b_sup, double* mu_1,
+                                   double* mu_ne, int* steps_host);
+chase_status chase_degrees(const double* resid_host, const double* ritz_host, int k, double b_sup,
+                           double mu_ne, double tol, int degree, const chase_opts* opts,
+                           int* degrees_host);
+
 /* Message of the last error raised on the calling thread ("" if none). */
 const char* chase_last_error(void);
 

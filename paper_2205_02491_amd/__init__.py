@@ -29,7 +29,8 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
             "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
             "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_eigvec_adjoint",
-            "chase_filter_adjoint", "chase_last_error"]
+            "chase_filter_adjoint", "chase_filter_coefficients", "chase_spectral_bounds",
+            "chase_degrees", "chase_last_error"]
 
 
 class ChaseError(RuntimeError):
@@ -107,6 +108,12 @@ def lib():
     L.chase_eigvec_adjoint.argtypes = [vp, vp, i64, vp, i64, ci, pd, vp, i64, vp, i64, cd, ci,
                                        ctypes.POINTER(ctypes.c_int), vp]
     L.chase_eigvec_adjoint.restype = ci
+    L.chase_filter_coefficients.argtypes = [ci, cd, cd, cd, pd]
+    L.chase_filter_coefficients.restype = ci
+    L.chase_spectral_bounds.argtypes = [pd, pd, ci, ci, i64, ci, pd, pd, pd, pi]
+    L.chase_spectral_bounds.restype = ci
+    L.chase_degrees.argtypes = [pd, pd, ci, cd, cd, cd, ci, ctypes.POINTER(Opts), pi]
+    L.chase_degrees.restype = ci
     L.chase_last_error.argtypes = []
     L.chase_last_error.restype = ctypes.c_char_p
     _lib = L
@@ -382,11 +389,54 @@ def chase_filter_adjoint(H, gY, dH, handle, want_gX=False):
     return gx.mH if gx is not None else None
 
 
+def _pd(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def chase_filter_coefficients(m, b_sup, mu_1, mu_ne):
+    """Scaled Chebyshev coefficients of Eq. (3) used by chase_filter: an
+    (m, 3) float64 array of (alpha, gamma, beta) per step."""
+    out = np.zeros((m, 3))
+    _check(lib().chase_filter_coefficients(int(m), float(b_sup), float(mu_1), float(mu_ne),
+                                           _pd(out)))
+    return out
+
+
+def chase_spectral_bounds(alpha, beta, n, n_e):
+    """b_sup, mu_1, mu_ne and per-run lengths from Lanczos tridiagonals
+    (alpha, beta: nvec x steps, one run per row, as chase_lanczos returns)."""
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    if a.ndim != 2 or a.shape != b.shape:
+        raise ValueError("alpha and beta must be 2-D arrays of one shape (nvec, steps)")
+    nvec, steps = a.shape
+    bs, m1, mne = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lens = (ctypes.c_int * nvec)()
+    _check(lib().chase_spectral_bounds(_pd(a), _pd(b), nvec, steps, int(n), int(n_e),
+                                       ctypes.byref(bs), ctypes.byref(m1), ctypes.byref(mne),
+                                       lens))
+    return bs.value, m1.value, mne.value, list(lens)
+
+
+def chase_degrees(resid, ritz, b_sup, mu_ne, tol, degree=20, opts: Opts | None = None):
+    """Per-vector filter degrees of Algorithm 1's degree step."""
+    r = np.ascontiguousarray(resid, dtype=np.float64).ravel()
+    t = np.ascontiguousarray(ritz, dtype=np.float64).ravel()
+    if r.shape != t.shape:
+        raise ValueError("resid and ritz must have the same length")
+    out = (ctypes.c_int * max(len(r), 1))()
+    _check(lib().chase_degrees(_pd(r), _pd(t), len(r), float(b_sup), float(mu_ne), float(tol),
+                               int(degree), ctypes.byref(opts) if opts is not None else None,
+                               out))
+    return np.array(out[: len(r)], dtype=np.int64)
+
+
 from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
            "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
            "chase_rayleigh_ritz",
-           "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint", "ChaseEigh",
+           "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint",
+           "chase_filter_coefficients", "chase_spectral_bounds", "chase_degrees", "ChaseEigh",
            "chase_eigh",
            "filtered_block", "lib", "EXPORTED"]

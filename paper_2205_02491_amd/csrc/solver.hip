@@ -887,6 +887,74 @@ size_t chase_workspace_bytes(chase_dtype dtype, int64_t n, int nev, int nex, con
 
 const char* chase_last_error(void) { return g_last_error.c_str(); }
 
+chase_status chase_filter_coefficients(int m, double b_sup, double mu_1, double mu_ne,
+                                       double* coef_host) {
+  return guarded([&] {
+    CHASE_REQUIRE(coef_host != nullptr, "NULL pointer argument");
+    CHASE_REQUIRE(m >= 1 && m <= kMaxDegree, "m out of range [1, 1000]");
+    CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
+                      mu_1 < mu_ne && mu_ne < b_sup,
+                  "need mu_1 < mu_ne < b_sup");
+    const std::vector<Coef> cf = cheb_coefficients(m, b_sup, mu_1, mu_ne);
+    for (int s = 0; s < m; ++s) {
+      coef_host[3 * s] = cf[s].alpha;
+      coef_host[3 * s + 1] = cf[s].gamma;
+      coef_host[3 * s + 2] = cf[s].beta;
+    }
+  });
+}
+
+chase_status chase_spectral_bounds(const double* alpha_host, const double* beta_host, int nvec,
+                                   int steps, int64_t n, int n_e, double* b_sup, double* mu_1,
+                                   double* mu_ne, int* steps_host) {
+  return guarded([&] {
+    CHASE_REQUIRE(alpha_host && beta_host && b_sup && mu_1 && mu_ne, "NULL pointer argument");
+    CHASE_REQUIRE(nvec >= 1 && steps >= 1, "nvec and steps must be >= 1");
+    CHASE_REQUIRE(n_e >= 1 && n_e <= n, "need 1 <= n_e <= n");
+    std::vector<double> a((size_t)steps * nvec), b((size_t)steps * nvec);
+    for (int r = 0; r < nvec; ++r)
+      for (int j = 0; j < steps; ++j) {
+        a[(size_t)j * nvec + r] = alpha_host[(size_t)r * steps + j];
+        b[(size_t)j * nvec + r] = beta_host[(size_t)r * steps + j];
+      }
+    for (size_t i = 0; i < a.size(); ++i)
+      CHASE_REQUIRE(std::isfinite(a[i]) && std::isfinite(b[i]) && b[i] >= 0.0,
+                    "alpha must be finite, beta finite and >= 0");
+    std::vector<int> lens;
+    const Bounds bd = lanczos_bounds(a, b, nvec, steps, n, n_e, &lens);
+    *b_sup = bd.b_sup;
+    *mu_1 = bd.mu_1;
+    *mu_ne = bd.mu_ne;
+    if (steps_host)
+      for (int r = 0; r < nvec; ++r) steps_host[r] = lens[r];
+  });
+}
+
+chase_status chase_degrees(const double* resid_host, const double* ritz_host, int k, double b_sup,
+                           double mu_ne, double tol, int degree, const chase_opts* opts,
+                           int* degrees_host) {
+  return guarded([&] {
+    CHASE_REQUIRE(resid_host && ritz_host && degrees_host, "NULL pointer argument");
+    CHASE_REQUIRE(k >= 0, "k must be >= 0");
+    CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_ne) && mu_ne < b_sup,
+                  "need mu_ne < b_sup");
+    CHASE_REQUIRE(tol > 0.0 && std::isfinite(tol), "tol must be > 0");
+    CHASE_REQUIRE(degree >= 2, "degree must be >= 2");
+    chase_opts o;
+    chase_default_opts(&o);
+    if (opts) o = *opts;
+    validate_opts(o);
+    const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
+    const int deg0 = degree + (degree & 1);
+    for (int a = 0; a < k; ++a) {
+      CHASE_REQUIRE(resid_host[a] > 0.0 && std::isfinite(resid_host[a]) &&
+                        std::isfinite(ritz_host[a]),
+                    "residuals must be finite and > 0, Ritz values finite");
+      degrees_host[a] = optimal_degree(resid_host[a], ritz_host[a], c, e, tol, o, deg0);
+    }
+  });
+}
+
 chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int nev, int nex,
                           const chase_opts* opts) {
   chase_handle_s* h = nullptr;

@@ -127,3 +127,64 @@ def test_colmajor_buffers_are_materialised_copies():
             assert torch.equal(b, x.conj().T.resolve_conj())
     with pytest.raises(ValueError, match="lazy conjugate"):
         pk._dev(torch.randn(3, dtype=torch.complex128).conj())
+
+
+def test_host_step_exports_match_oracle():
+    """The three host-side exports (no GPU involved) against the oracle on
+    the same Lanczos tridiagonals, coefficients and degree inputs."""
+    import numpy as np
+
+    import gen
+    import oracle
+    pk = _lib()
+    g = np.random.Generator(np.random.PCG64(11))
+    n, steps, nv, ne = 300, 25, 4, 40
+    h = gen.planted(gen.spectrum_uniform_iid(n, g), gen.haar(n, g, True))
+    s = gen.gaussian(g, (n, nv), True)
+    runs = oracle.lanczos_runs(h, s, steps)
+    a = np.zeros((nv, steps))
+    b = np.zeros((nv, steps))
+    for r, (ar, br) in enumerate(runs):
+        a[r, : len(ar)] = ar
+        b[r, : len(br)] = br
+    b_ref, m1_ref, mne_ref, _ = oracle.spectral_bounds(h, s, steps, ne)
+    b_sup, mu_1, mu_ne, lens = pk.chase_spectral_bounds(a, b, n, ne)
+    assert lens == [len(ar) for ar, _ in runs]
+    np.testing.assert_allclose([b_sup, mu_1, mu_ne], [b_ref, m1_ref, mne_ref], rtol=0, atol=1e-13)
+
+    cf = pk.chase_filter_coefficients(20, b_sup, mu_1, mu_ne)
+    ref = np.array(oracle.filter_coefficients(20, b_sup, mu_1, mu_ne)).reshape(20, 3)
+    np.testing.assert_allclose(cf, ref, rtol=1e-15, atol=0)
+
+    c, e = 0.5 * (b_sup + mu_ne), 0.5 * (b_sup - mu_ne)
+    res = 10 ** g.uniform(-11, 0, 200)
+    ritz = g.uniform(mu_1, mu_ne, 200)
+    opts = oracle.Options()
+    got = pk.chase_degrees(res, ritz, b_sup, mu_ne, 1e-10, 20)
+    want = np.array([int(d) for d in oracle.degrees(res, ritz, c, e, 1e-10, opts, 20)])
+    np.testing.assert_array_equal(got, want)
+    fixed = pk.chase_degrees(res, ritz, b_sup, mu_ne, 1e-10, 17,
+                             opts=pk.default_opts(optimize_degree=0))
+    assert (fixed == 18).all()
+    assert len(pk.chase_degrees([], [], b_sup, mu_ne, 1e-10)) == 0
+
+
+def test_host_step_exports_reject_bad_arguments():
+    import numpy as np
+    pk = _lib()
+    bad_coef = [(0, 1.0, -1.0, 0.0), (1001, 1.0, -1.0, 0.0), (5, 1.0, 0.5, 0.2),
+                (5, float("nan"), -1.0, 0.0)]
+    for args in bad_coef:
+        with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+            pk.chase_filter_coefficients(*args)
+    a = np.ones((2, 5))
+    with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+        pk.chase_spectral_bounds(a, -a, 100, 10)            # negative beta
+    with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+        pk.chase_spectral_bounds(a, a, 100, 101)            # n_e > n
+    with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+        pk.chase_degrees([0.0], [0.1], 1.0, 0.5, 1e-10)     # zero residual
+    with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+        pk.chase_degrees([1e-3], [0.1], 0.5, 1.0, 1e-10)    # mu_ne > b_sup
+    with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
+        pk.chase_degrees([1e-3], [0.1], 1.0, 0.5, 1e-10, opts=pk.default_opts(max_deg=0))
