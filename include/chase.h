@@ -85,7 +85,17 @@ typedef struct chase_opts {
                           converged pairs lock at once, the first degrees are
                           optimised, mixed modes use the defect form from the
                           start).  Not in Algorithm 1; default 0            */
-  int reserved[6];
+  int fp64_tail;       /* mixed modes, start block's (plain) low-precision
+                          pass: run its last fp64_tail steps with FP64
+                          products, which damp the earlier steps' rounding
+                          errors so the pass can reach FP64 residuals.
+                          -1 (default): automatic, the steps that shrink a
+                          rounding floor (2^-14 split-BF16, 2^-17 FP32) to
+                          tol at the growth rate of the density-of-states
+                          estimate of the nev-th eigenvalue, used only if
+                          fewer than the degree; 0: off; > 0: that many
+                          (capped at the degree).  Ignored with initial_rr  */
+  int reserved[5];
 } chase_opts;
 
 typedef struct chase_stats {
@@ -104,6 +114,11 @@ typedef struct chase_stats {
   double t_lanczos_gemv;   /* summed HIP-event time of the Lanczos block GEMVs */
   int64_t lanczos_gemv_launches; /* number of Lanczos block GEMV launches   */
   double lanczos_gemv_bytes; /* bytes of H read by them (one pass per launch) */
+  double t_filter_kernels_low; /* the part of t_filter_kernels spent in
+                                  low-precision filter GEMMs                */
+  int64_t filter_launches_low; /* the low-precision ones of filter_launches */
+  int fp64_tail;           /* FP64 steps at the end of the start block's
+                              low-precision pass (0: none)                  */
 } chase_stats;
 
 typedef struct chase_handle_s* chase_handle_t;

@@ -45,7 +45,7 @@ class Opts(ctypes.Structure):
                 ("lanczos_vecs", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("filter_prec", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
-                ("reserved", ctypes.c_int * 6)]
+                ("fp64_tail", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -59,7 +59,9 @@ class Stats(ctypes.Structure):
                 ("mu_1", ctypes.c_double), ("mu_ne", ctypes.c_double),
                 ("qr_shifted", ctypes.c_int), ("qr_householder", ctypes.c_int),
                 ("t_lanczos_gemv", ctypes.c_double), ("lanczos_gemv_launches", ctypes.c_int64),
-                ("lanczos_gemv_bytes", ctypes.c_double)]
+                ("lanczos_gemv_bytes", ctypes.c_double),
+                ("t_filter_kernels_low", ctypes.c_double),
+                ("filter_launches_low", ctypes.c_int64), ("fp64_tail", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -148,6 +148,7 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
   CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
+  CHASE_REQUIRE(o.fp64_tail >= -1 && o.fp64_tail <= kMaxDegree, "fp64_tail out of range [-1,1000]");
   CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32 ||
                     o.filter_prec == CHASE_PREC_BF16X3,
                 "unknown filter_prec");
@@ -260,13 +261,18 @@ void split_h(chase_handle_s* h, const void* H, int64_t ldh, hipStream_t st) {
 }
 
 // X (n x k, ld ldx) <- p_{m_a}(H) x_a ; Wb (n x k, ld ldw) ping-pong scratch.
-// degrees non-decreasing, even, >= 2.
+// degrees non-decreasing, even, >= 2.  With a low precision `prec`, steps
+// s >= fp64_from run with FP64 products instead (timed into *ft64): the
+// rounding errors of the earlier low-precision steps are then damped by the
+// remaining steps like any other unwanted component.
 void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t ldx, void* Wb,
                 int64_t ldw, int k, const int* deg, double b_sup, double mu_1, double mu_ne,
-                Prec prec, bool tape, FilterTiming& ft, hipStream_t st) {
+                Prec prec, bool tape, FilterTiming& ft, hipStream_t st, int fp64_from = 0,
+                FilterTiming* ft64 = nullptr) {
   if (k <= 0) return;
   const int64_t n = h->n;
   const int mmax = deg[k - 1];
+  if (prec == PREC_F64 || fp64_from <= 0 || !ft64) fp64_from = mmax + 1;
   const std::vector<Coef> cf = cheb_coefficients(mmax, b_sup, mu_1, mu_ne);
   const void* Ah = H;
   int64_t lda = ldh;
@@ -293,25 +299,29 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     const int a0 = step_first_col(deg, k, s);
     const int cols = k - a0;
     if (cols <= 0) continue;
+    const bool low = s < fp64_from;
     void* src = (s & 1) ? X : Wb;  // X_{s-1}
     void* dst = (s & 1) ? Wb : X;  // X_s over X_{s-2}
     const int64_t lds = (s & 1) ? ldx : ldw, ldd = (s & 1) ? ldw : ldx;
-    GemmArgs g = gargs(n, cols, n, Ah, lda, off(src, a0 * lds, h->esz), lds,
+    GemmArgs g = gargs(n, cols, n, low ? Ah : H, low ? lda : ldh, off(src, a0 * lds, h->esz), lds,
                        off(dst, a0 * ldd, h->esz), ldd);
     g.alpha = cf[s - 1].alpha;
     g.gamma = cf[s - 1].gamma;
     g.beta = cf[s - 1].beta;
-    g.a_f32 = a_f32;
-    if (bsteps) {
+    g.a_f32 = low ? a_f32 : 0;
+    if (bsteps && low) {
+      // the epilogue emits the next step's operand split only if that step
+      // also runs on split-BF16 products
       const int a1 = step_first_col(deg, k, s + 1);
-      bsteps->prepare(g, cols, (s < mmax && a1 < k) ? a1 - a0 : -1, st);
+      bsteps->prepare(g, cols, (s < mmax && a1 < k && s + 1 < fp64_from) ? a1 - a0 : -1, st);
     }
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
-    gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
+    gemm(h->cplx, low ? prec : PREC_F64, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
-    if (bsteps) bsteps->advance(g);
-    ft.matvecs += cols;
-    ft.launches += 1;
+    if (bsteps && low) bsteps->advance(g);
+    FilterTiming& fs = low ? ft : *ft64;
+    fs.matvecs += cols;
+    fs.launches += 1;
     if (tape)
       copy_cols(h->cplx, off(dst, a0 * ldd, h->esz), ldd,
                 off(h->tape, ((int64_t)s * k + a0) * n, h->esz), n, n, cols, st);
@@ -322,7 +332,7 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     if (k - a0 <= 0) continue;
     float ms = 0.f;
     CHASE_HIP(hipEventElapsedTime(&ms, h->evs[2 * (s - 1)], h->evs[2 * (s - 1) + 1]));
-    ft.ktime += ms * 1e-3;
+    (s < fp64_from ? ft : *ft64).ktime += ms * 1e-3;
   }
   if (tape) {
     h->tape_deg.assign(deg, deg + k);
@@ -672,7 +682,8 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
 
   // Lanczos spectral bounds
   const int steps = (int)std::min<int64_t>(o.lanczos_steps, n);
-  Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, nullptr, nullptr, nullptr, st,
+  std::vector<double> lz_a, lz_b;
+  Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, &lz_a, &lz_b, nullptr, st,
                          &stats.t_lanczos_gemv);
   stats.lanczos_gemv_launches = steps;
   stats.lanczos_gemv_bytes = (double)steps * (double)n * (double)n * (double)h->esz;
@@ -687,6 +698,32 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   const bool mixed = o.filter_prec != CHASE_PREC_FP64;
   const Prec plow = o.filter_prec == CHASE_PREC_BF16X3 ? PREC_BF16X3 : PREC_F32;
   const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
+  // FP64 tail of the start block's low-precision pass: the rounding error of
+  // the low-precision products (relative size `floor` after a plain pass)
+  // sits in all directions; each later step damps its unwanted part relative
+  // to the nev-th wanted vector by rho = |t| + sqrt(t^2 - 1), t = (lambda_nev
+  // - c)/e (the growth rate of the degree step), lambda_nev estimated from the
+  // Lanczos density of states.  The tail is the number of final FP64 steps
+  // that bring floor down to tol; it is used only when it is shorter than the
+  // pass (when the spectrum is hard, the defect-correction passes of the
+  // later iterations do that work instead).
+  int fp64_tail = 0;
+  if (mixed && !o.initial_rr) {
+    if (o.fp64_tail > 0) {
+      fp64_tail = std::min(o.fp64_tail, deg0);
+    } else if (o.fp64_tail < 0) {
+      const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
+      const double floor = plow == PREC_BF16X3 ? 0x1p-14 : 0x1p-17;
+      const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
+      const double t = e > 0.0 ? (lam_nev - c) / e : 0.0;
+      if (t < -1.0 && floor > tol) {
+        const double rho = -t + std::sqrt(t * t - 1.0);
+        const double j = std::ceil(std::log(floor / tol) / std::log(rho));
+        if (std::isfinite(j) && j < deg0) fp64_tail = (int)j;
+      }
+    }
+  }
+  stats.fp64_tail = fp64_tail;
   if (plow == PREC_F32 && mixed && h->H32) to_f32(cplx, H, ldh, h->H32, n, st);
   if (plow == PREC_BF16X3) split_h(h, H, ldh, st);
 
@@ -811,7 +848,8 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     if (ka - n64 > 0) {
       if (it == 0 && !have_ritz)  // start block: no Ritz pairs yet, plain low-precision products
         run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
-                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st);
+                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st,
+                   fp64_tail > 0 ? m[ne - 1] - fp64_tail + 1 : 0, &ft64);
       else  // Ritz vectors: defect-correction form with low-precision products
         run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,
                           off(h->Rres, (int64_t)(L + n64) * n, h->esz), n, h->W, h->Z,
@@ -846,6 +884,8 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   stats.matvecs_fp64 = ft64.matvecs;
   stats.matvecs_low = ftlo.matvecs;
   stats.t_filter_kernels = ft64.ktime + ftlo.ktime;
+  stats.t_filter_kernels_low = ftlo.ktime;
+  stats.filter_launches_low = ftlo.launches;
   stats.filter_launches = ft64.launches + ftlo.launches;
   stats.filter_flops = (cplx ? 8.0 : 2.0) * (double)n * (double)n *
                        (double)(ft64.matvecs + ftlo.matvecs);
@@ -873,6 +913,7 @@ void chase_default_opts(chase_opts* o) {
   o->max_iter = 50;
   o->filter_prec = CHASE_PREC_FP64;
   o->switch_tol = 0.0;
+  o->fp64_tail = -1;
   o->verbose = 0;
 }
 

@@ -39,7 +39,7 @@ def test_default_opts():
     pk = _lib()
     o = pk.default_opts()
     assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
-            o.max_iter, o.filter_prec, o.initial_rr) == (36, 2, 1, 25, 4, 50, 0, 0)
+            o.max_iter, o.filter_prec, o.initial_rr, o.fp64_tail) == (36, 2, 1, 25, 4, 50, 0, 0, -1)
 
 
 def test_workspace_bytes_matches_one_gpu_memory_estimate():
@@ -95,6 +95,10 @@ def test_create_rejects_bad_sizes_without_gpu():
     o = pk.default_opts(initial_rr=2)
     st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
     assert st == pk.ERR_ARG and b"initial_rr" in L.chase_last_error()
+    for bad in (-2, 1001):
+        o = pk.default_opts(fp64_tail=bad)
+        st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
+        assert st == pk.ERR_ARG and b"fp64_tail" in L.chase_last_error()
     assert L.chase_eigvec_adjoint(None, None, 0, None, 0, 1, None, None, 0, None, 0, 1e-10, 10,
                                   None, None) == pk.ERR_ARG
     assert b"handle" in L.chase_last_error()

@@ -40,3 +40,51 @@ def test_mixed_solve_meets_fp64_bar(pk, cplx, prec):
     gap = p.lam[p.nev] - p.lam[p.nev - 1]
     bound = (np.linalg.norm(r) + np.linalg.norm(p.H @ v_o - v_o * ev_o[None, :])) / gap
     assert subspace_sin(v, v_o) <= max(2 * bound, 1e-8)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("tail", [-1, 8, 0])
+def test_start_pass_fp64_tail(pk, prec, tail):
+    """Start block's low-precision pass with its last steps in FP64 (forced
+    length, automatic, off) on a geometric spectrum where one FP64 pass
+    converges: the result meets the FP64 bar against the oracle; with the
+    automatic or a long enough tail the mixed solve takes the oracle's
+    iteration count, and the tail's matrix-vector products are counted as
+    FP64 ones."""
+    announce(f"mixed solve fp64_tail={tail} n=2400 prec={prec}")
+    p = gen.make_geometric(n=2400, nev=120, nex=36, n_geo=144, cfg=44)
+    ev_o, v_o, r_o, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
+    o = pk.default_opts(filter_prec=pk.PREC_FP32 if prec == "fp32" else pk.PREC_BF16X3,
+                        fp64_tail=tail)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S), opts=o)
+    assert st["converged"]
+    norm = max(abs(p.lam[0]), abs(p.lam[-1]))
+    assert np.max(np.abs(ev - ev_o)) <= 1e-10 * norm
+    assert np.all(res <= p.tol)
+    ne = p.nev + p.nex
+    if tail == 0:
+        assert st["fp64_tail"] == 0
+    elif tail > 0:
+        assert st["fp64_tail"] == tail
+    else:
+        assert 0 < st["fp64_tail"] < p.deg
+    if st["fp64_tail"] > 0:
+        assert st["matvecs_fp64"] >= st["fp64_tail"] * ne
+        assert st["matvecs_low"] >= (p.deg - st["fp64_tail"]) * ne
+    if tail != 0:
+        assert st["iterations"] <= st_o.iterations + 1
+    v = to_np(vec)
+    assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) <= 1e-12
+
+
+def test_automatic_fp64_tail_off_on_uniform_spectrum(pk):
+    """On a uniform spectrum the wanted end grows too slowly for a short FP64
+    tail to damp the low-precision rounding: the automatic rule leaves the
+    pass in low precision."""
+    announce("mixed solve fp64_tail auto, uniform n=1000")
+    p = gen.make_uniform(n=1000, nev=100, nex=40, cfg=21)
+    o = pk.default_opts(filter_prec=pk.PREC_BF16X3)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S), opts=o)
+    assert st["converged"] and st["fp64_tail"] == 0
