@@ -23,16 +23,18 @@ sys.path.insert(0, ROOT)
 METRIC = "solve s @resid≤1e-10 & filter TFLOP/s (% MFMA peak), FP64 vs mixed"
 # dense MFMA peaks of one MI355X (TFLOP/s) for the arithmetic each filter
 # mode executes: FP64, FP32, BF16 (split-BF16 runs on the BF16 matrix cores)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
 # executed MFMA FLOPs per algorithmic FLOP (8 per complex multiply-add):
 # three real products per complex product (Gauss) for FP64/FP32, twelve BF16
-# products (four real products x hi*hi, hi*lo, lo*hi) for split-BF16
-EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0}
-PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+# products (four real products x hi*hi, hi*lo, lo*hi) for split-BF16, eight
+# for its two-term form (the block as bf16: hi*hi, lo*hi)
+EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0, "bf16x2": 2.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
 KERNEL_NAME = {
     "fp64": "gemm_kernel<double,double,complex,N,N,CHEB,8,Gauss,128x64> (FP64 MFMA 16x16x4)",
     "fp32": "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss,128x64> (FP32 MFMA 16x16x4)",
-    "bf16x3": "gemm_bf16x3_kernel<complex> (BF16 MFMA 32x32x16, 256x128 tiles)",
+    "bf16x3": "gemm_bf16x3_kernel<complex, 3 terms> (BF16 MFMA 32x32x16, 256x128 tiles)",
+    "bf16x2": "gemm_bf16x3_kernel<complex, 2 terms> (BF16 MFMA 32x32x16, 256x128 tiles)",
 }
 
 # HBM bytes per filter launch from rocprofv3 PMC runs (FETCH_SIZE x 2.0 and
@@ -297,7 +299,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="geometric20k", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="all", choices=["fp64", "fp32", "bf16x3", "both", "all"],
+    ap.add_argument("--prec", default="all",
+                    choices=["fp64", "fp32", "bf16x3", "bf16x2", "both", "all"],
                     help="filter modes to time: both = fp64 + fp32, all = fp64 + fp32 + bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--warm-start", action="store_true",
@@ -358,7 +361,7 @@ def main():
     lam = prob["lam"]
     norm = max(abs(lam[0]), abs(lam[-1]))
 
-    precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3"]}.get(args.prec,
+    precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"]}.get(args.prec,
                                                                           [args.prec])
     results = {}
     for prec in precs:
@@ -442,7 +445,8 @@ def main():
         "metric": METRIC, "value": r["solve_s"], "unit": "s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["solve_s"] * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp64": "c128", "fp32": "c64/c128", "bf16x3": "bf16x3/c128"}[main_prec],
+        "dtype": {"fp64": "c128", "fp32": "c64/c128", "bf16x3": "bf16x3/c128",
+                  "bf16x2": "bf16x2/c128"}[main_prec],
         "data": "synthetic planted-spectrum Hermitian (seeded, generated on the GPU)",
         "config": {"workload": f"{args.workload}", "n": n, "nev": nev, "nex": nex,
                    "degree": wl["deg"], "tol": wl["tol"], "filter": main_prec,
@@ -464,7 +468,7 @@ def main():
                          "avg_launch_ms": r["lanczos_gemv_ms"],
                          "bytes_per_launch": n * n * (16 if H.is_complex() else 8)},
     }
-    for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3")):
+    for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3"), ("bf16x2", "mixed_bf16x2")):
         if low not in results or main_prec == low:
             continue
         m = results[low]

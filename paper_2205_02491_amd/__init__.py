@@ -21,7 +21,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libchase.so")
 
 C128, F64 = 0, 1
-PREC_FP64, PREC_FP32, PREC_BF16X3 = 0, 1, 2
+PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16X2 = 0, 1, 2, 3
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC = range(6)
 _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
            4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}

@@ -53,7 +53,8 @@ enum Epi { EPI_STORE = 0, EPI_CHEB = 1, EPI_SPLITK = 2, EPI_RESID = 3 };
 // operands rounded to float when staged in LDS, FP32 accumulation) or split
 // BF16 (three BF16 MFMAs per real product on hi/lo splits of both operands,
 // FP32 accumulation; operands in the s8 layout below).
-enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2 };
+enum Prec { PREC_F64 = 0, PREC_F32 = 1, PREC_BF16X3 = 2, PREC_BF16X2 = 3 };
+inline bool is_split_bf16(Prec p) { return p == PREC_BF16X3 || p == PREC_BF16X2; }
 
 struct GemmArgs {
   int64_t M, N, K;
@@ -126,7 +127,9 @@ void split_s8(bool cplx, bool conj, const void* src, int64_t lds, int64_t rows, 
               int64_t cols_pad, void* dst, int64_t groups, hipStream_t st);
 // Filter step C = alpha (A B - gamma B) + beta C [+ colcoef F] with split-BF16
 // products (GemmArgs a_s8, b_s8, s8_groups; M = rows of C, K <= 8*s8_groups).
-void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st);
+// terms = 3: hi*hi + hi*lo + lo*hi; terms = 2: the block operand as bf16
+// only (hi*hi + lo_H*hi).
+void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st, int terms = 3);
 
 // Launch the tile GEMM. cplx selects complex (c128) vs real (double) data.
 void gemm(bool cplx, Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g,

@@ -541,10 +541,10 @@ void splitk_plan(int64_t M, int64_t N, int64_t K, int* splits, int64_t* kslice, 
 
 void gemm(bool cplx, Prec prec, Op opa, Op opb, Epi epi, const GemmArgs& g, hipStream_t st) {
   if (g.M <= 0 || g.N <= 0) return;
-  if (prec == PREC_BF16X3) {
+  if (is_split_bf16(prec)) {
     CHASE_REQUIRE(opa == OP_N && opb == OP_N && epi == EPI_CHEB,
                   "split-BF16 products exist only for the filter step");
-    return gemm_bf16x3(cplx, g, st);
+    return gemm_bf16x3(cplx, g, st, prec == PREC_BF16X2 ? 2 : 3);
   }
   if (cplx)
     dispatch<true>(prec, opa, opb, epi, g, st);

@@ -198,9 +198,10 @@ struct TailPlan {
   float* ws;
 };
 
-template <bool CPLX, bool SPLIT>
+template <bool CPLX, bool SPLIT, int TERMS>
 __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles_n, int ntiles,
                                                            TailPlan tp) {
+  static_assert(TERMS == 2 || TERMS == 3, "two or three split terms");
   constexpr int P = CPLX ? 4 : 2;
   constexpr int CB = (KC / 8) * P * 16;  // bytes of one column in one chunk
   constexpr int PIECES = CB / 16;
@@ -299,12 +300,16 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
           f16v re = acc_re[fi][fj], im = acc_im[fi][fj];
-          re = mfma(xf[fj][1], tf[fi][0], re);
-          im = mfma(xf[fj][3], tf[fi][0], im);
+          if constexpr (TERMS == 3) {  // block lo planes
+            re = mfma(xf[fj][1], tf[fi][0], re);
+            im = mfma(xf[fj][3], tf[fi][0], im);
+          }
           re = mfma(xf[fj][0], tf[fi][1], re);
           im = mfma(xf[fj][2], tf[fi][1], im);
-          re = mfma(nxi_l, tf[fi][2], re);
-          im = mfma(xf[fj][1], tf[fi][2], im);
+          if constexpr (TERMS == 3) {
+            re = mfma(nxi_l, tf[fi][2], re);
+            im = mfma(xf[fj][1], tf[fi][2], im);
+          }
           re = mfma(nxi_h, tf[fi][3], re);
           im = mfma(xf[fj][0], tf[fi][3], im);
           re = mfma(xf[fj][0], tf[fi][0], re);
@@ -321,7 +326,7 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
 #pragma unroll
         for (int fi = 0; fi < 2; ++fi) {
           f16v re = acc_re[fi][fj];
-          re = mfma(xf[fj][1], tf[fi][0], re);
+          if constexpr (TERMS == 3) re = mfma(xf[fj][1], tf[fi][0], re);
           re = mfma(xf[fj][0], tf[fi][1], re);
           re = mfma(xf[fj][0], tf[fi][0], re);
           acc_re[fi][fj] = re;
@@ -423,7 +428,7 @@ int device_cus() {
   return n;
 }
 
-void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st) {
+void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st, int terms) {
   if (g.M <= 0 || g.N <= 0) return;
   CHASE_REQUIRE(g.a_s8 && g.b_s8 && g.s8_groups > 0 && g.s8_groups % (S8_KPAD / 8) == 0,
                 "split-BF16 operands missing");
@@ -452,15 +457,22 @@ void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st) {
       }
     }
   }
+  CHASE_REQUIRE(terms == 2 || terms == 3, "split-BF16 products take two or three terms");
   const int whole = ntiles - tp.rem;
   if (whole > 0) {
     const int grid_x = (whole + 7) / 8 * 8;
-    if (cplx)
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false>), dim3(grid_x), dim3(NTHR), 0, st, g,
+    if (cplx && terms == 3)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, 3>), dim3(grid_x), dim3(NTHR), 0, st, g,
                          tiles_n, whole, tp);
+    else if (cplx)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, 2>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, whole, tp);
+    else if (terms == 3)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, 3>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, whole, tp);
     else
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false>), dim3(grid_x), dim3(NTHR), 0, st, g,
-                         tiles_n, whole, tp);
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, false, 2>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, whole, tp);
     CHASE_HIP(hipGetLastError());
   }
   if (tp.rem > 0) {
@@ -469,12 +481,20 @@ void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st) {
     const int64_t elems = (int64_t)tp.rem * TBM * TBN;
     const unsigned fin = (unsigned)std::min<int64_t>((elems + 255) / 256, 8192);
     if (cplx) {
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true>), dim3(grid_x), dim3(NTHR), 0, st, g,
-                         tiles_n, ntiles, tp);
+      if (terms == 3)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 3>), dim3(grid_x), dim3(NTHR), 0, st,
+                           g, tiles_n, ntiles, tp);
+      else
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 2>), dim3(grid_x), dim3(NTHR), 0, st,
+                           g, tiles_n, ntiles, tp);
       hipLaunchKernelGGL(tail_finish_k<true>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
     } else {
-      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true>), dim3(grid_x), dim3(NTHR), 0, st, g,
-                         tiles_n, ntiles, tp);
+      if (terms == 3)
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 3>), dim3(grid_x), dim3(NTHR), 0, st,
+                           g, tiles_n, ntiles, tp);
+      else
+        hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 2>), dim3(grid_x), dim3(NTHR), 0, st,
+                           g, tiles_n, ntiles, tp);
       hipLaunchKernelGGL(tail_finish_k<false>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
     }
     CHASE_HIP(hipGetLastError());

@@ -132,7 +132,7 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
   s.lz = lanczos_bytes(cplx, n, o.lanczos_vecs, o.lanczos_steps, &s.lz_splits);
   if (o.filter_prec == CHASE_PREC_FP32)
     s.h32 = (size_t)n * n * esz / 2 + (size_t)n * ne * esz;
-  else if (o.filter_prec == CHASE_PREC_BF16X3)
+  else if (o.filter_prec == CHASE_PREC_BF16X3 || o.filter_prec == CHASE_PREC_BF16X2)
     s.h32 = s8_bytes(cplx, n, s8_pad(n, S8_COLS_A)) +
             2 * s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) + s8_tail_bytes(cplx) +
             (size_t)n * ne * esz;
@@ -150,7 +150,7 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
   CHASE_REQUIRE(o.fp64_tail >= -1 && o.fp64_tail <= kMaxDegree, "fp64_tail out of range [-1,1000]");
   CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32 ||
-                    o.filter_prec == CHASE_PREC_BF16X3,
+                    o.filter_prec == CHASE_PREC_BF16X3 || o.filter_prec == CHASE_PREC_BF16X2,
                 "unknown filter_prec");
 }
 
@@ -211,7 +211,10 @@ struct FilterTiming {
 };
 
 Prec to_prec(int p) {
-  return p == CHASE_PREC_BF16X3 ? PREC_BF16X3 : p == CHASE_PREC_FP32 ? PREC_F32 : PREC_F64;
+  return p == CHASE_PREC_BF16X3   ? PREC_BF16X3
+         : p == CHASE_PREC_BF16X2 ? PREC_BF16X2
+         : p == CHASE_PREC_FP32   ? PREC_F32
+                                  : PREC_F64;
 }
 
 // Split-BF16 operands of the filter steps.  The split of H is the
@@ -227,7 +230,7 @@ struct Bf16Steps {
   bool ready = false; // cur already holds this step's operand
   explicit Bf16Steps(chase_handle_s* hh) : h(hh), cur(hh->Xs8), other(hh->Xs8b) {
     CHASE_REQUIRE(h->Hs8 && h->Xs8 && h->Xs8b, "split-BF16 products need a handle created with "
-                                              "filter_prec = CHASE_PREC_BF16X3");
+                                              "filter_prec = CHASE_PREC_BF16X3 or BF16X2");
   }
   // g: the step's GEMM (B = its FP64 operand, cols columns); next_col0 >= 0:
   // the next step multiplies this step's output columns [next_col0, cols)
@@ -256,7 +259,7 @@ int step_first_col(const int* deg, int k, int s) {
 // split of conj(H) = H^T (H Hermitian) for the split-BF16 products
 void split_h(chase_handle_s* h, const void* H, int64_t ldh, hipStream_t st) {
   CHASE_REQUIRE(h->Hs8, "split-BF16 products need a handle created with "
-                        "filter_prec = CHASE_PREC_BF16X3");
+                        "filter_prec = CHASE_PREC_BF16X3 or BF16X2");
   split_s8(h->cplx, true, H, ldh, h->n, h->n, s8_pad(h->n, S8_COLS_A), h->Hs8, h->s8_groups, st);
 }
 
@@ -294,7 +297,7 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
     h->evs.push_back(e);
   }
   std::unique_ptr<Bf16Steps> bsteps;
-  if (prec == PREC_BF16X3) bsteps.reset(new Bf16Steps(h));
+  if (is_split_bf16(prec)) bsteps.reset(new Bf16Steps(h));
   for (int s = 1; s <= mmax; ++s) {
     const int a0 = step_first_col(deg, k, s);
     const int cols = k - a0;
@@ -391,7 +394,7 @@ void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, i
   axpby_cols(h->cplx, h->d_coef + k, R, ldr, nullptr, W1, n, n, k, st);
   fill_zero(W2, (int64_t)n * k * (int64_t)h->esz, st);
   std::unique_ptr<Bf16Steps> bsteps;
-  if (prec == PREC_BF16X3) bsteps.reset(new Bf16Steps(h));
+  if (is_split_bf16(prec)) bsteps.reset(new Bf16Steps(h));
   for (int s = 2; s <= mmax; ++s) {
     const int a0 = step_first_col(deg, k, s);
     const int cols = k - a0;
@@ -696,7 +699,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   const double norm_est = bd.norm_lower > 0 ? bd.norm_lower : std::fabs(bd.b_sup);
 
   const bool mixed = o.filter_prec != CHASE_PREC_FP64;
-  const Prec plow = o.filter_prec == CHASE_PREC_BF16X3 ? PREC_BF16X3 : PREC_F32;
+  const Prec plow = to_prec(o.filter_prec) == PREC_F64 ? PREC_F32 : to_prec(o.filter_prec);
   const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
   // FP64 tail of the start block's low-precision pass: the rounding error of
   // the low-precision products (relative size `floor` after a plain pass)
@@ -713,7 +716,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       fp64_tail = std::min(o.fp64_tail, deg0);
     } else if (o.fp64_tail < 0) {
       const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
-      const double floor = plow == PREC_BF16X3 ? 0x1p-14 : 0x1p-17;
+      const double floor = plow == PREC_BF16X3 ? 0x1p-14 : plow == PREC_BF16X2 ? 0x1p-6 : 0x1p-17;
       const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
       const double t = e > 0.0 ? (lam_nev - c) / e : 0.0;
       if (t < -1.0 && floor > tol) {
@@ -725,7 +728,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   }
   stats.fp64_tail = fp64_tail;
   if (plow == PREC_F32 && mixed && h->H32) to_f32(cplx, H, ldh, h->H32, n, st);
-  if (plow == PREC_BF16X3) split_h(h, H, ldh, st);
+  if (is_split_bf16(plow)) split_h(h, H, ldh, st);
 
   CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
   std::vector<int> m(ne, deg0);
@@ -1066,7 +1069,7 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     if (o.filter_prec == CHASE_PREC_FP32) {
       if (with_h32) h->H32 = dev_alloc(h, h32_bytes);
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
-    } else if (o.filter_prec == CHASE_PREC_BF16X3) {
+    } else if (o.filter_prec == CHASE_PREC_BF16X3 || o.filter_prec == CHASE_PREC_BF16X2) {
       h->s8_groups = s8_groups(n);
       h->Hs8 = dev_alloc(h, s8_bytes(h->cplx, n, s8_pad(n, S8_COLS_A)));
       const size_t xb = s8_bytes(h->cplx, n, s8_pad(ne, S8_COLS_B));
@@ -1156,10 +1159,12 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     CHASE_REQUIRE(H && X && degrees, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldx >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
-    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3,
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3 ||
+                      prec == CHASE_PREC_BF16X2,
                   "unknown precision");
-    CHASE_REQUIRE(prec != CHASE_PREC_BF16X3 || h->Hs8,
-                  "CHASE_PREC_BF16X3 needs a handle created with that filter_prec");
+    CHASE_REQUIRE((prec != CHASE_PREC_BF16X3 && prec != CHASE_PREC_BF16X2) || h->Hs8,
+                  "split-BF16 products need a handle created with filter_prec = "
+                  "CHASE_PREC_BF16X3 or CHASE_PREC_BF16X2");
     CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
                       mu_1 < mu_ne && mu_ne < b_sup,
                   "need mu_1 < mu_ne < b_sup");
@@ -1172,7 +1177,7 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     set_stream(h, st);
     if (record_tape) ensure_tape(h, k, degrees[k - 1]);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
-    if (prec == CHASE_PREC_BF16X3) split_h(h, H, ldh, st);
+    if (prec == CHASE_PREC_BF16X3 || prec == CHASE_PREC_BF16X2) split_h(h, H, ldh, st);
     FilterTiming ft;
     h->tape_valid = false;
     run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne, to_prec(prec),
@@ -1190,10 +1195,12 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
     CHASE_REQUIRE(H && V && R && theta && degrees, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldv >= h->n && ldr >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
-    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3,
+    CHASE_REQUIRE(prec == CHASE_PREC_FP64 || prec == CHASE_PREC_FP32 || prec == CHASE_PREC_BF16X3 ||
+                      prec == CHASE_PREC_BF16X2,
                   "unknown precision");
-    CHASE_REQUIRE(prec != CHASE_PREC_BF16X3 || h->Hs8,
-                  "CHASE_PREC_BF16X3 needs a handle created with that filter_prec");
+    CHASE_REQUIRE((prec != CHASE_PREC_BF16X3 && prec != CHASE_PREC_BF16X2) || h->Hs8,
+                  "split-BF16 products need a handle created with filter_prec = "
+                  "CHASE_PREC_BF16X3 or CHASE_PREC_BF16X2");
     CHASE_REQUIRE(std::isfinite(b_sup) && std::isfinite(mu_1) && std::isfinite(mu_ne) &&
                       mu_1 < mu_ne && mu_ne < b_sup,
                   "need mu_1 < mu_ne < b_sup");
@@ -1206,7 +1213,7 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
     hipStream_t st = static_cast<hipStream_t>(stream);
     set_stream(h, st);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
-    if (prec == CHASE_PREC_BF16X3) split_h(h, H, ldh, st);
+    if (prec == CHASE_PREC_BF16X3 || prec == CHASE_PREC_BF16X2) split_h(h, H, ldh, st);
     FilterTiming ft;
     run_filter_defect(h, H, ldh, V, ldv, R, ldr, h->W, h->Z, k, degrees, theta, b_sup, mu_1,
                       mu_ne, to_prec(prec), ft, st);

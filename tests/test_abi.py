@@ -73,6 +73,9 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
         o3 = pk.default_opts(filter_prec=pk.PREC_BF16X3)
         b3 = pk.chase_workspace_bytes(n, nev, nex, cplx=cplx, opts=o3)
         assert b3 - pk.chase_workspace_bytes(n, nev, nex, cplx=cplx) == extra
+        # the two-term form keeps the same splits (it only skips MFMAs)
+        o2 = pk.default_opts(filter_prec=pk.PREC_BF16X2)
+        assert pk.chase_workspace_bytes(n, nev, nex, cplx=cplx, opts=o2) == b3
     assert pk.chase_workspace_bytes(10, 8, 4) == 0      # nev + nex > n
     assert pk.chase_workspace_bytes(10, 0, 4) == 0
 
@@ -89,7 +92,7 @@ def test_create_rejects_bad_sizes_without_gpu():
     o = pk.default_opts(lanczos_vecs=9)
     st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
     assert st == pk.ERR_ARG
-    o = pk.default_opts(filter_prec=3)
+    o = pk.default_opts(filter_prec=4)
     st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
     assert st == pk.ERR_ARG and b"filter_prec" in L.chase_last_error()
     o = pk.default_opts(initial_rr=2)
