@@ -42,7 +42,7 @@ KERNEL_NAME = {
 # source they were measured on (sha256 prefix of csrc/gemm.hip).
 MEASURED_TRAFFIC = {
     ("geometric20k", "fp64"): {"fetch_gb": 54.55, "write_gb": 0.416, "columns": 1300,
-                               "gemm_sha256": "7e1c3994d286dd91",
+                               "gemm_sha256": "c0bdc1127171d3e2",
                                "source": "profiles/filter_fp64_geometric20k_hbm_traffic.md"},
 }
 
