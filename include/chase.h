@@ -59,9 +59,11 @@ typedef enum chase_dtype { CHASE_C128 = 0, CHASE_F64 = 1 } chase_dtype;
  * split of H (n*n*8 bytes complex, n*n*4 real, padded) and of the block.
  * CHASE_PREC_BF16X2: the same split of H, the block rounded to bf16 (its hi
  * part only): a real product is hi*hi + lo*hi, two MFMAs instead of three
- * (about 2^-9 relative per product; same memory as BF16X3).  Where the
- * spectrum rather than precision limits convergence it takes about as many
- * matrix-vector products as BF16X3 at two thirds of the MFMA work.
+ * (about 2^-9 relative per product; same memory as BF16X3).  In a solve it
+ * is used for the defect-correction passes only (the start block's plain
+ * pass runs with three terms): where the spectrum rather than precision
+ * limits convergence it takes about as many matrix-vector products as
+ * BF16X3 at two thirds of the MFMA work.
  * In all low-precision modes the start block is filtered with the plain
  * recurrence, Ritz vectors in the defect-correction form (see
  * chase_filter_ritz), whose rounding error shrinks with the residual; a
@@ -96,8 +98,7 @@ typedef struct chase_opts {
                           products, which damp the earlier steps' rounding
                           errors so the pass can reach FP64 residuals.
                           -1 (default): automatic, the steps that shrink a
-                          rounding floor (2^-14 BF16X3, 2^-6 BF16X2, 2^-17
-                          FP32) to
+                          rounding floor (2^-14 split-BF16, 2^-17 FP32) to
                           tol at the growth rate of the density-of-states
                           estimate of the nev-th eigenvalue, used only if
                           fewer than the degree; 0: off; > 0: that many

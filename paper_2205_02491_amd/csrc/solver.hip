@@ -700,6 +700,11 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
 
   const bool mixed = o.filter_prec != CHASE_PREC_FP64;
   const Prec plow = to_prec(o.filter_prec) == PREC_F64 ? PREC_F32 : to_prec(o.filter_prec);
+  // The start block's plain pass carries an absolute rounding floor (about
+  // 1e-2 of the result with the block rounded to bf16), the defect-form
+  // passes one relative to the residual: the two-term split-BF16 mode runs
+  // its start pass with three terms and only the defect-form passes with two.
+  const Prec pstart = plow == PREC_BF16X2 ? PREC_BF16X3 : plow;
   const double tau_sw = o.switch_tol > 0 ? o.switch_tol : 0.0;
   // FP64 tail of the start block's low-precision pass: the rounding error of
   // the low-precision products (relative size `floor` after a plain pass)
@@ -716,7 +721,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       fp64_tail = std::min(o.fp64_tail, deg0);
     } else if (o.fp64_tail < 0) {
       const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
-      const double floor = plow == PREC_BF16X3 ? 0x1p-14 : plow == PREC_BF16X2 ? 0x1p-6 : 0x1p-17;
+      const double floor = pstart == PREC_BF16X3 ? 0x1p-14 : 0x1p-17;
       const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
       const double t = e > 0.0 ? (lam_nev - c) / e : 0.0;
       if (t < -1.0 && floor > tol) {
@@ -851,7 +856,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     if (ka - n64 > 0) {
       if (it == 0 && !have_ritz)  // start block: no Ritz pairs yet, plain low-precision products
         run_filter(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n, h->W, n, ka - n64,
-                   &m[L + n64], b_sup, mu_1, mu_ne, plow, false, ftlo, st,
+                   &m[L + n64], b_sup, mu_1, mu_ne, pstart, false, ftlo, st,
                    fp64_tail > 0 ? m[ne - 1] - fp64_tail + 1 : 0, &ft64);
       else  // Ritz vectors: defect-correction form with low-precision products
         run_filter_defect(h, H, ldh, off(h->V, (int64_t)(L + n64) * n, h->esz), n,

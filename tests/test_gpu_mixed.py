@@ -46,16 +46,16 @@ def test_mixed_solve_meets_fp64_bar(pk, cplx, prec):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x2"])
-@pytest.mark.parametrize("tail", [-1, 8, 0])
-def test_start_pass_fp64_tail(pk, prec, tail):
+@pytest.mark.parametrize("tail,cplx", [(-1, True), (8, True), (0, True), (-1, False)])
+def test_start_pass_fp64_tail(pk, prec, tail, cplx):
     """Start block's low-precision pass with its last steps in FP64 (forced
     length, automatic, off) on a geometric spectrum where one FP64 pass
     converges: the result meets the FP64 bar against the oracle; with the
     automatic or a long enough tail the mixed solve takes the oracle's
     iteration count, and the tail's matrix-vector products are counted as
     FP64 ones."""
-    announce(f"mixed solve fp64_tail={tail} n=2400 prec={prec}")
-    p = gen.make_geometric(n=2400, nev=120, nex=36, n_geo=144, cfg=44)
+    announce(f"mixed solve fp64_tail={tail} n=2400 prec={prec} cplx={cplx}")
+    p = gen.make_geometric(n=2400, nev=120, nex=36, n_geo=144, cplx=cplx, cfg=44)
     ev_o, v_o, r_o, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
     o = pk.default_opts(filter_prec=CODE[prec], fp64_tail=tail)
     ev, vec, res, st = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
@@ -74,9 +74,7 @@ def test_start_pass_fp64_tail(pk, prec, tail):
     if st["fp64_tail"] > 0:
         assert st["matvecs_fp64"] >= st["fp64_tail"] * ne
         assert st["matvecs_low"] >= (p.deg - st["fp64_tail"]) * ne
-    if tail == -1 or (tail > 0 and prec != "bf16x2"):
-        # (8 FP64 steps do not damp the two-term rounding floor, ~1e-2, to
-        # tol; the automatic rule takes more)
+    if tail != 0:
         assert st["iterations"] <= st_o.iterations + 1
     v = to_np(vec)
     assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) <= 1e-12
