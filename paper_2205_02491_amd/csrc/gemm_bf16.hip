@@ -4,7 +4,11 @@
 // real product is formed from three BF16 MFMAs with FP32 accumulation:
 //   a b ~ a_hi b_hi + a_hi b_lo + a_lo b_hi
 // (the dropped a_lo b_lo term is below 2^-16 |a b|).  A complex product is
-// four real ones, i.e. twelve MFMAs.
+// four real ones, i.e. twelve MFMAs.  The two-term form (TERMS = 2) uses the
+// block operand's hi part only, a b ~ a_hi b_hi + a_lo b_hi (the block
+// rounded to bf16, 2^-9 relative): eight MFMAs per complex product; the LDS
+// reads of the block's lo planes drop out with their MFMAs, the global-to-LDS
+// copies still carry them (the operand layout is shared with TERMS = 3).
 //
 // Operand storage (the "s8" layout, made by split_s8): a K x C matrix is
 // stored column by column; the K rows are zero-padded to a multiple of 16 and
@@ -49,7 +53,7 @@
 //
 // Measured on one MI355X (n=30000, 2000 columns, 1888 tiles): 32.9 ms per
 // step with the tail (34.3 ms without), 438 TFLOP/s algorithmic (1.3
-// PFLOP/s of BF16 MFMA work).  n=20000 with 1300 columns: 10.4 ms (11.2 ms
+// PFLOP/s of BF16 MFMA work); two-term form 23.5 ms.  n=20000 with 1300 columns: 10.4 ms (11.2 ms
 // without the tail).  The matrix cores are busy 54% of the time at the
 // clock this kernel runs at (about 1.95 GHz with random operands:
 // power-limited; 2.3 GHz in a pure-MFMA loop); the same MFMA block alone
