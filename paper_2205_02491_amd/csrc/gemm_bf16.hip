@@ -6,9 +6,9 @@
 // (the dropped a_lo b_lo term is below 2^-16 |a b|).  A complex product is
 // four real ones, i.e. twelve MFMAs.  The two-term form (TERMS = 2) uses the
 // block operand's hi part only, a b ~ a_hi b_hi + a_lo b_hi (the block
-// rounded to bf16, 2^-9 relative): eight MFMAs per complex product; the LDS
-// reads of the block's lo planes drop out with their MFMAs, the global-to-LDS
-// copies still carry them (the operand layout is shared with TERMS = 3).
+// rounded to bf16, 2^-9 relative): eight MFMAs per complex product; the
+// block's lo planes are neither copied to LDS nor read (the operand layout
+// is shared with TERMS = 3).
 //
 // Operand storage (the "s8" layout, made by split_s8): a K x C matrix is
 // stored column by column; the K rows are zero-padded to a multiple of 16 and
@@ -253,6 +253,10 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
       const int blk = wave * LOADS + e;
       const int col0 = blk * BLK_COLS;
       const int pc = slot(col0 + bc, lane % PIECES);  // slot() is an involution in p
+      // two terms: the block's lo planes (odd pieces) are never read, so they
+      // are not copied (the wait before the barrier drains all loads, so the
+      // count of issued loads does not matter)
+      if (TERMS == 2 && col0 >= TBM && (pc & 1)) continue;
       const char* src = (col0 < TBM ? srcT + (int64_t)col0 * colbytes
                                     : srcX + (int64_t)(col0 - TBM) * colbytes) + c * CB + pc * 16;
       __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
