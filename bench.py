@@ -308,6 +308,8 @@ def main():
                          "Hermitian) solved cold and warm-started from the previous "
                          "eigenvectors, in each timed filter mode")
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--max-deg", type=int, default=None,
+                    help="cap of the optimised filter degree (library default 36)")
     ap.add_argument("--gen-elementary", action="store_true",
                     help="build Q from 64 elementary reflectors (no factorization) with the "
                          "workload's spectrum; for counter-collection runs, where rocprofv3 "
@@ -366,6 +368,8 @@ def main():
     results = {}
     for prec in precs:
         opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if args.verbose else 0)
+        if args.max_deg is not None:
+            opts.max_deg = args.max_deg
         handle = pk.Handle(n, nev, nex, H.dtype, opts)
         for w in range(args.warmup):
             ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
@@ -450,6 +454,7 @@ def main():
         "data": "synthetic planted-spectrum Hermitian (seeded, generated on the GPU)",
         "config": {"workload": f"{args.workload}", "n": n, "nev": nev, "nex": nex,
                    "degree": wl["deg"], "tol": wl["tol"], "filter": main_prec,
+                   "max_deg": args.max_deg if args.max_deg is not None else 36,
                    "parallelism": "single GPU"},
         "filter_tflops": r["filter_tflops"], "filter_frac_peak": r["filter_tflops"] / peak,
         "filter_peak_tflops": peak,
