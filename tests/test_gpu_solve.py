@@ -218,3 +218,39 @@ def test_initial_rr_on_converged_start_block_locks_without_filtering(pk):
     assert st["converged"] and st["iterations"] == 0
     assert st["matvecs_fp64"] == 0 and np.all(res <= 1e-10)
     assert np.max(np.abs(ev - p.lam[:30])) <= 1e-12
+
+
+@pytest.mark.parametrize("kind", ["uniform", "121", "wilkinson"])
+def test_solve_table1_suite_matches_oracle_counts(pk, kind):
+    """The paper's Table 1 matrix types (real symmetric, n=1200, 90 wanted):
+    Uniform (epsilon = 1e-4, planted with a Haar orthogonal Q), the (1-2-1)
+    and the Wilkinson tridiagonal matrices stored dense.  The paper reports
+    that its CPU and GPU builds take the same iterations and Matvecs on such
+    inputs (Table 2); here the FP64 GPU solve against the oracle: iterations
+    within one, Matvecs within 2% when the iteration counts agree, and equal
+    eigenvalues; (1-2-1) also against its closed-form spectrum.  (The
+    Geometric type with epsilon = 1e-4 clusters the 90 lowest eigenvalues
+    within 2e-5 of each other and does not converge in 50 iterations at
+    this size.)"""
+    n, nev, nex = 1200, 90, 30
+    announce(f"solve Table 1 {kind} n={n} nev={nev} nex={nex}")
+    if kind in ("121", "wilkinson"):
+        p = gen.make_tridiag(kind, n, nev, nex, cfg=50)
+    else:
+        lam = gen.table1_uniform(n)
+        H = gen.planted(lam, gen.haar(n, gen.rng(51, gen.SLOT_Q), False))
+        v0, s = gen.start_blocks(51, n, nev + nex, 4, False)
+        p = gen.Problem(kind, H, lam, None, v0, s, nev, nex, 20, 1e-10)
+    ev_o, v_o, r_o, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
+    ev, vec, res, st = pk.chase_solve(to_gpu(p.H), nev, nex, p.tol, p.deg, to_gpu(p.V0),
+                                      to_gpu(p.S))
+    assert st["converged"] and st_o.converged
+    norm = max(abs(ev_o[0]), float(np.max(np.abs(np.linalg.eigvalsh(p.H)[[0, -1]]))))
+    assert np.max(np.abs(ev - ev_o)) <= 1e-10 * norm
+    if p.lam is not None:
+        assert np.max(np.abs(ev - p.lam[:nev])) <= 2e-10 * norm
+    assert abs(st["iterations"] - st_o.iterations) <= 1, (st["iterations"], st_o.iterations)
+    if st["iterations"] == st_o.iterations:
+        assert abs(st["matvecs_fp64"] - st_o.matvecs) <= 0.02 * st_o.matvecs, \
+            (st["matvecs_fp64"], st_o.matvecs)
+    assert np.all(res <= p.tol)
