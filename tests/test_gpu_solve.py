@@ -107,13 +107,13 @@ def test_solve_tiny_edge(pk):
     assert abs(ev[0] - w[0]) < 1e-10 * np.max(np.abs(w))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x2"])
 @pytest.mark.parametrize("cplx", [True, False])
 def test_solve_tiny_edge_mixed(pk, prec, cplx):
     """Smallest legal sizes with low-precision filter products: n=3 and n=17
     (less than one 16-row group of the split layout past a multiple of 16),
     nev=1, nex=1; the FP64 residual bar still holds."""
-    code = {"fp32": pk.PREC_FP32, "bf16x3": pk.PREC_BF16X3}[prec]
+    code = {"fp32": pk.PREC_FP32, "bf16x3": pk.PREC_BF16X3, "bf16x2": pk.PREC_BF16X2}[prec]
     for n in (3, 17):
         announce(f"solve tiny mixed n={n} prec={prec} cplx={cplx}")
         g = np.random.Generator(np.random.PCG64(300 + n + cplx))
@@ -175,13 +175,14 @@ def test_solve_warm_start_sequence(pk):
                                                                 st_c["matvecs_fp64"])
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x3", "bf16x2"])
 def test_solve_warm_start_initial_rayleigh_ritz(pk, prec):
     """Warm start with Rayleigh-Ritz on the start block (initial_rr): the
     first filter uses degrees optimised from the start block's residuals, so
     the perturbed problem needs fewer Matvecs than a cold start (measured
     0.70x FP64, 0.67x split-BF16 here); the pairs still match the oracle and
-    meet the tolerance."""
+    meet the tolerance.  With the two-term mode every pass, the first one
+    included, is a two-term defect-form pass (no Matvec ratio asserted)."""
     announce(f"warm start + initial RR n=1000 prec={prec}")
     p = gen.make_uniform(n=1000, nev=100, nex=40, cfg=15)
     ev1, vec1, _, _ = pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
@@ -190,7 +191,7 @@ def test_solve_warm_start_initial_rayleigh_ritz(pk, prec):
     E = gen.gaussian(g, (p.n, p.n), True)
     H2 = p.H + 1e-5 * (E + E.conj().T) / (2 * np.linalg.norm(E, 2))
     v0w = np.concatenate([to_np(vec1), p.V0[:, p.nev:]], axis=1)
-    fp = pk.PREC_FP64 if prec == "fp64" else pk.PREC_BF16X3
+    fp = {"fp64": pk.PREC_FP64, "bf16x3": pk.PREC_BF16X3, "bf16x2": pk.PREC_BF16X2}[prec]
     o_cold = pk.default_opts(filter_prec=fp)
     o_rr = pk.default_opts(filter_prec=fp, initial_rr=1)
     _, _, _, st_c = pk.chase_solve(to_gpu(H2), p.nev, p.nex, p.tol, p.deg, to_gpu(p.V0),
@@ -202,7 +203,10 @@ def test_solve_warm_start_initial_rayleigh_ritz(pk, prec):
     assert np.max(np.abs(ev_w - ev_o)) <= 1e-10
     mv_c = st_c["matvecs_fp64"] + st_c["matvecs_low"]
     mv_w = st_w["matvecs_fp64"] + st_w["matvecs_low"]
-    assert mv_w < 0.75 * mv_c, (mv_w, mv_c)
+    if prec != "bf16x2":
+        assert mv_w < 0.75 * mv_c, (mv_w, mv_c)
+    else:
+        assert st_w["matvecs_low"] > 0
     v = to_np(vec_w)
     assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) <= 1e-12
 
