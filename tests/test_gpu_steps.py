@@ -243,14 +243,23 @@ def test_filter_ritz_bf16x3_error_scales_with_residual(pk, prec):
 
 
 def test_bf16x3_needs_split_handle(pk):
-    """A handle created for FP64 filtering holds no split of H."""
+    """A handle created for FP64 filtering holds no split of H (either
+    split-BF16 form is refused); a handle made for one split-BF16 form runs
+    the other (same buffers)."""
     n = 300
     h, lam, q, g = _problem(n, True, 17)
     x = gen.gaussian(g, (n, 8), True)
+    deg = np.full(8, 4, np.int32)
     handle = pk.Handle(n, 6, 2)
-    with pytest.raises(pk.ChaseError):
-        pk.chase_filter(to_gpu(h), to_gpu(x), np.full(8, 4, np.int32), 1.02, -1.0, -0.6,
-                        prec=pk.PREC_BF16X3, handle=handle)
+    for prec in (pk.PREC_BF16X3, pk.PREC_BF16X2):
+        with pytest.raises(pk.ChaseError, match="split-BF16"):
+            pk.chase_filter(to_gpu(h), to_gpu(x), deg, 1.02, -1.0, -0.6, prec=prec, handle=handle)
+    h3 = pk.Handle(n, 6, 2, filter_prec=pk.PREC_BF16X3)
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, 1.02, -1.0, -0.6, prec=pk.PREC_BF16X2,
+                            handle=h3)
+    y_ref, _ = oracle.chebyshev_filter(h, x, deg, 1.02, -1.0, -0.6)
+    err = np.linalg.norm(to_np(y) - y_ref, axis=0) / np.linalg.norm(y_ref, axis=0)
+    assert mv == 32 and np.all(err < ERR["bf16x2"][0])
 
 
 # ------------------------------------------------------------------ Lanczos
