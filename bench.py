@@ -5,7 +5,8 @@ problem, inputs resident in HBM before timing starts.
 Default workload: n=20000 complex128, lowest 1200 eigenvalues geometric
 (-1 + 10^(-4(1-i/1200))), the rest uniform in [0,1], Haar Q; nev=1000,
 nex=300, degree 20, tol 1e-10; FP64 filter (and, as further measurements on
-the same matrix, the mixed filters: FP32 products, split-BF16 products).
+the same matrix, the mixed filters: FP32 products, split-BF16 products with
+three terms, and the two-term split-BF16 mode).
 
 Prints one JSON line (see the README of the bench contract in the design doc).
 """
