@@ -153,4 +153,13 @@ int optimal_degree(double res, double ritz, double c, double e, double tol, cons
   return m;
 }
 
+int fp64_tail_steps(double floor, double lam_nev, double c, double e, double tol, int deg) {
+  if (!(e > 0.0) || !(floor > tol) || !(tol > 0.0)) return 0;
+  const double t = (lam_nev - c) / e;
+  if (!(t < -1.0)) return 0;
+  const double rho = -t + std::sqrt(t * t - 1.0);
+  const double j = std::ceil(std::log(floor / tol) / std::log(rho));
+  return (std::isfinite(j) && j < deg) ? (int)j : 0;
+}
+
 }  // namespace chase

@@ -30,4 +30,11 @@ std::vector<Coef> cheb_coefficients(int m, double b_sup, double mu_1, double mu_
 int optimal_degree(double res, double ritz, double c, double e, double tol, const chase_opts& o,
                    int deg);
 
+// Number of final FP64 steps of a low-precision filter pass of degree deg
+// (even) that damp a rounding floor `floor` down to tol at the growth rate
+// rho = |t| + sqrt(t^2 - 1), t = (lam_nev - c)/e, of the nev-th wanted
+// eigenvalue (estimate lam_nev); 0 when that takes deg steps or more, when
+// lam_nev is not below the damped interval or floor <= tol.
+int fp64_tail_steps(double floor, double lam_nev, double c, double e, double tol, int deg);
+
 }  // namespace chase

@@ -722,13 +722,8 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     } else if (o.fp64_tail < 0) {
       const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
       const double floor = pstart == PREC_BF16X3 ? 0x1p-14 : 0x1p-17;
-      const double c = 0.5 * (b_sup + mu_ne), e = 0.5 * (b_sup - mu_ne);
-      const double t = e > 0.0 ? (lam_nev - c) / e : 0.0;
-      if (t < -1.0 && floor > tol) {
-        const double rho = -t + std::sqrt(t * t - 1.0);
-        const double j = std::ceil(std::log(floor / tol) / std::log(rho));
-        if (std::isfinite(j) && j < deg0) fp64_tail = (int)j;
-      }
+      fp64_tail = fp64_tail_steps(floor, lam_nev, 0.5 * (b_sup + mu_ne), 0.5 * (b_sup - mu_ne),
+                                  tol, deg0);
     }
   }
   stats.fp64_tail = fp64_tail;

@@ -35,4 +35,8 @@ int shim_degree(double res, double ritz, double c, double e, double tol, int max
   o.optimize_degree = optimize;
   return chase::optimal_degree(res, ritz, c, e, tol, o, deg);
 }
+
+int shim_tail(double floor, double lam_nev, double c, double e, double tol, int deg) {
+  return chase::fp64_tail_steps(floor, lam_nev, c, e, tol, deg);
+}
 }

@@ -28,6 +28,8 @@ def shim(tmp_path_factory):
     lib.shim_coefs.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, pd]
     lib.shim_degree.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int] * 4
     lib.shim_degree.restype = ctypes.c_int
+    lib.shim_tail.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int]
+    lib.shim_tail.restype = ctypes.c_int
     return lib
 
 
@@ -119,3 +121,40 @@ int main() {
                     os.path.join(csrc, "hostmath.cpp"), "-o", str(exe)], check=True)
     r = subprocess.run([str(exe)], capture_output=True, text=True)
     assert r.returncode == 0 and r.stdout.strip() == "ok", r.stderr
+
+
+def test_fp64_tail_rule(shim):
+    """Automatic FP64 tail of a low-precision start pass: the fewest final
+    steps j with floor / rho^j <= tol, rho the Chebyshev growth rate at the
+    nev-th eigenvalue estimate (found here by counting steps, not by the
+    library's logarithm formula); 0 when j would reach the degree, when the
+    estimate is not below the damped interval [c - e, c + e], or when the
+    floor is already below tol."""
+    g = np.random.Generator(np.random.PCG64(8))
+    for _ in range(3000):
+        c, e = g.uniform(-1, 1), g.uniform(0.05, 2)
+        lam = c - e * (1 + 10 ** g.uniform(-4, 1))
+        floor, tol, deg = 2.0 ** -int(g.integers(6, 20)), 10.0 ** g.uniform(-12, -8), 20
+        t = (lam - c) / e
+        rho = abs(t) + np.sqrt(t * t - 1)
+        j = 1
+        while floor / rho ** j > tol * (1 + 1e-12) and j < 10 ** 6:
+            j += 1
+        want = j if j < deg else 0
+        got = shim.shim_tail(floor, lam, c, e, tol, deg)
+        assert got == want or abs(np.log(floor / tol) / np.log(rho) - round(np.log(floor / tol) / np.log(rho))) < 1e-9, \
+            (floor, lam, c, e, tol, got, want)
+    # off: estimate inside the damped interval, floor below tol, no interval
+    assert shim.shim_tail(2.0 ** -14, 0.0, 0.0, 1.0, 1e-10, 20) == 0
+    assert shim.shim_tail(1e-12, -5.0, 0.0, 1.0, 1e-10, 20) == 0
+    assert shim.shim_tail(2.0 ** -14, -5.0, 0.0, 0.0, 1e-10, 20) == 0
+    # the oracle's Lanczos estimates on gen.make_geometric(n=3000, nev=150,
+    # nex=45, n_geo=180, cfg=41), the problem on which the floors were
+    # calibrated (b_sup 1.51457, mu_ne 0.0074903, density-of-states estimate
+    # of lambda_150 -0.857573; rho = 4.049): 10 steps for split BF16, 9 for
+    # FP32, none once the degree is too small for that
+    b_sup, mu_ne, lam_nev = 1.51457, 0.0074903, -0.857573
+    c, e = (b_sup + mu_ne) / 2, (b_sup - mu_ne) / 2
+    assert shim.shim_tail(2.0 ** -14, lam_nev, c, e, 1e-10, 20) == 10
+    assert shim.shim_tail(2.0 ** -17, lam_nev, c, e, 1e-10, 20) == 9
+    assert shim.shim_tail(2.0 ** -14, lam_nev, c, e, 1e-10, 10) == 0
