@@ -8,7 +8,10 @@ nex=300, degree 20, tol 1e-10; FP64 filter (and, as further measurements on
 the same matrix, the mixed filters: FP32 products, split-BF16 products with
 three terms, and the two-term split-BF16 mode).
 
-Prints one JSON line (see the README of the bench contract in the design doc).
+Prints one JSON line: the FP64 solve time as the value, the filter's
+algorithmic TFLOP/s against the FP64 MFMA peak (roofline), the Lanczos block
+GEMV's GB/s against the HBM peak, the mixed-precision solves on the same
+matrix, and the CPU oracle's filter rate on a bounded sample.
 """
 from __future__ import annotations
 
