@@ -98,7 +98,8 @@ typedef struct chase_opts {
                           products, which damp the earlier steps' rounding
                           errors so the pass can reach FP64 residuals.
                           -1 (default): automatic, the steps that shrink a
-                          rounding floor (2^-14 split-BF16, 2^-17 FP32) to
+                          rounding floor (2^-14 split-BF16, 2^-17
+                          sqrt(max(1, n/3000)) FP32) to
                           tol at the growth rate of the density-of-states
                           estimate of the nev-th eigenvalue, used only if
                           fewer than the degree; 0: off; > 0: that many

@@ -721,7 +721,12 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       fp64_tail = std::min(o.fp64_tail, deg0);
     } else if (o.fp64_tail < 0) {
       const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
-      const double floor = pstart == PREC_BF16X3 ? 0x1p-14 : 0x1p-17;
+      // floors calibrated at n = 3000: split BF16 is dominated by the
+      // operands' 16-bit representation; FP32 by the accumulation of its
+      // n-term sums, whose rounding grows like sqrt(n)
+      const double floor = pstart == PREC_BF16X3
+                               ? 0x1p-14
+                               : 0x1p-17 * std::sqrt(std::max(1.0, (double)n / 3000.0));
       fp64_tail = fp64_tail_steps(floor, lam_nev, 0.5 * (b_sup + mu_ne), 0.5 * (b_sup - mu_ne),
                                   tol, deg0);
     }
