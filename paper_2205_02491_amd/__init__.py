@@ -99,7 +99,7 @@ def lib():
     L.chase_filter_ritz.argtypes = [vp, vp, i64, vp, i64, vp, i64, pd, ci, pi, cd, cd, cd, ci,
                                     pi64, vp]
     L.chase_filter_ritz.restype = ci
-    L.chase_qr.argtypes = [vp, vp, i64, ci, ci, vp]
+    L.chase_qr.argtypes = [vp, vp, i64, ci, ci, pi, pi, vp]
     L.chase_qr.restype = ci
     L.chase_rayleigh_ritz.argtypes = [vp, vp, i64, vp, i64, ci, cd, pd, pd, vp]
     L.chase_rayleigh_ritz.restype = ci
@@ -174,6 +174,46 @@ def _colmajor(x):
     return x.mH.resolve_conj().clone(memory_format=torch.contiguous_format)
 
 
+def _check_square(H):
+    """H: a square, contiguous complex128 or float64 tensor (the library
+    reads n x n entries with leading dimension n)."""
+    if H.dim() != 2 or H.shape[0] != H.shape[1]:
+        raise ValueError(f"H must be a square matrix, got shape {tuple(H.shape)}")
+    if not H.is_contiguous():
+        raise ValueError("H must be contiguous")
+    _dtype_code(H)
+
+
+def _check_handle(handle, n, dtype, nev=None, nex=None, k=None):
+    """The handle's sizes and element type must match the arguments: the
+    library sizes every read and write by the handle."""
+    import torch
+    if handle.n != n:
+        raise ValueError(f"handle was created for n={handle.n}, the arguments have n={n}")
+    if handle.cplx != (dtype == torch.complex128):
+        raise ValueError(f"handle was created for {'complex128' if handle.cplx else 'float64'}, "
+                         f"the arguments are {dtype}")
+    if nev is not None and (handle.nev, handle.nex) != (nev, nex):
+        raise ValueError(f"handle was created for nev={handle.nev}, nex={handle.nex}; "
+                         f"the call asks for nev={nev}, nex={nex}")
+    if k is not None and not 1 <= k <= handle.nev + handle.nex:
+        raise ValueError(f"{k} columns do not fit the handle (1 <= k <= nev+nex = "
+                         f"{handle.nev + handle.nex})")
+
+
+def _check_block(X, n, k=None, name="X"):
+    if X.dim() != 2 or X.shape[0] != n or (k is not None and X.shape[1] != k):
+        want = f"({n}, {k})" if k is not None else f"({n}, k)"
+        raise ValueError(f"{name} must have shape {want}, got {tuple(X.shape)}")
+
+
+def _host_vec(a, length, dtype, name):
+    out = np.ascontiguousarray(np.asarray(a, dtype=dtype)).ravel()
+    if out.shape[0] != length:
+        raise ValueError(f"{name} must have {length} entries, got {out.shape[0]}")
+    return out
+
+
 class Handle:
     """Owns the library handle and its device workspace (allocated once)."""
 
@@ -184,6 +224,7 @@ class Handle:
         self.n, self.nev, self.nex = int(n), int(nev), int(nex)
         self.opts = opts or default_opts(**kw)
         self.dtype = dtype
+        self.tape_k = None
         h = ctypes.c_void_p()
         _check(lib().chase_create(ctypes.byref(h), C128 if self.cplx else F64, self.n,
                                   self.nev, self.nex, ctypes.byref(self.opts)))
@@ -226,13 +267,18 @@ def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, h
     (n, nev), resid numpy[nev], stats dict).  NOCONV returns the best pairs
     with stats['converged'] = False."""
     import torch
+    _check_square(H)
     n = H.shape[0]
-    assert H.shape == (n, n) and H.is_contiguous()
-    _dtype_code(H)
+    if handle is not None:
+        _check_handle(handle, n, H.dtype, nev, nex)
     h, own = _ensure_handle(handle, H, nev, nex, opts)
     try:
         ne = nev + nex
         nl = h.opts.lanczos_vecs
+        if V0 is not None:
+            _check_block(V0, n, ne, "V0")
+        if S is not None:
+            _check_block(S, n, nl, "S")
         if V0 is None or S is None:
             g = torch.Generator(device=H.device)
             g.manual_seed(seed)
@@ -263,12 +309,16 @@ def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, h
 def chase_lanczos(H, S, steps=None, handle=None, n_e=None, opts=None):
     """Lanczos bounds from the start vectors S (n x nvec).  Returns
     (b_sup, mu_1, mu_ne, alpha[nvec, steps], beta[nvec, steps], lengths)."""
+    _check_square(H)
     n = H.shape[0]
+    _check_block(S, n, None, "S")
     nvec = S.shape[1]
     if handle is None:
-        assert n_e is not None
+        if n_e is None:
+            raise ValueError("n_e (= nev + nex) is needed when no handle is given")
         nev = max(1, n_e // 2)
         handle = Handle(n, nev, n_e - nev, H.dtype, opts)
+    _check_handle(handle, n, H.dtype)
     steps = steps or handle.opts.lanczos_steps
     sc = _colmajor(S.to(H.dtype))
     a = np.zeros((nvec, steps))
@@ -287,18 +337,23 @@ def chase_filter(H, X, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64, record_tape=
                  handle=None):
     """Chebyshev filter of the columns of X (n x k) with per-column even,
     non-decreasing degrees.  Returns (Y, matvecs); X is not modified."""
-    import torch
-    n, k = X.shape
+    _check_square(H)
+    n = H.shape[0]
+    _check_block(X, n, None, "X")
+    k = X.shape[1]
     if handle is None:
         handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1 if k > 1 else 1, H.dtype,
                         filter_prec=int(prec))
+    _check_handle(handle, n, H.dtype, k=k)
     buf = _colmajor(X.to(H.dtype))
-    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    deg = _host_vec(degrees, k, np.int32, "degrees")
     mv = ctypes.c_int64()
     _check(lib().chase_filter(handle.ptr, _dev(H), n, _dev(buf), n, k,
                               deg.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), float(b_sup),
                               float(mu_1), float(mu_ne), int(prec), int(bool(record_tape)),
                               ctypes.byref(mv), _stream()))
+    # the recorded tape (the adjoint reads k columns of its gradient)
+    handle.tape_k = k if record_tape else None
     return buf.mH, mv.value
 
 
@@ -306,13 +361,18 @@ def chase_filter_ritz(H, V, R, theta, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP6
                       handle=None):
     """p(H) V in the defect-correction form for vectors V (n x k) with shifts
     theta (k) and residuals R = H V - V diag(theta).  Returns (Y, matvecs)."""
-    n, k = V.shape
+    _check_square(H)
+    n = H.shape[0]
+    _check_block(V, n, None, "V")
+    k = V.shape[1]
+    _check_block(R, n, k, "R")
     if handle is None:
         handle = Handle(n, max(1, k - 1) if k > 1 else 1, 1, H.dtype, filter_prec=int(prec))
+    _check_handle(handle, n, H.dtype, k=k)
     vbuf = _colmajor(V.to(H.dtype))
     rbuf = _colmajor(R.to(H.dtype))
-    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
-    deg = np.ascontiguousarray(np.asarray(degrees, dtype=np.int32))
+    th = _host_vec(theta, k, np.float64, "theta")
+    deg = _host_vec(degrees, k, np.int32, "degrees")
     mv = ctypes.c_int64()
     _check(lib().chase_filter_ritz(handle.ptr, _dev(H), n, _dev(vbuf), n, _dev(rbuf), n,
                                    th.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), k,
@@ -322,22 +382,34 @@ def chase_filter_ritz(H, V, R, theta, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP6
     return vbuf.mH, mv.value
 
 
-def chase_qr(X, locked=0, handle=None):
-    """Orthonormalise X (n x k) keeping its first `locked` columns."""
+def chase_qr(X, locked=0, handle=None, return_stats=False):
+    """Orthonormalise X (n x k) keeping its first `locked` columns.  With
+    return_stats, also returns {'shifted_passes', 'householder'}."""
+    if X.dim() != 2:
+        raise ValueError(f"X must be a matrix, got shape {tuple(X.shape)}")
     n, k = X.shape
     if handle is None:
         handle = Handle(n, max(1, k - 1), 1, X.dtype)
+    _check_handle(handle, n, X.dtype, k=k)
     buf = _colmajor(X)
-    _check(lib().chase_qr(handle.ptr, _dev(buf), n, k, int(locked), _stream()))
+    sp, hh = ctypes.c_int(), ctypes.c_int()
+    _check(lib().chase_qr(handle.ptr, _dev(buf), n, k, int(locked), ctypes.byref(sp),
+                          ctypes.byref(hh), _stream()))
+    if return_stats:
+        return buf.mH, {"shifted_passes": sp.value, "householder": hh.value}
     return buf.mH
 
 
 def chase_rayleigh_ritz(H, Q, norm_scale=1.0, handle=None):
     """Rayleigh-Ritz + residuals on the orthonormal Q (n x k): returns
     (ritz numpy[k], V tensor (n, k), resid numpy[k])."""
-    n, k = Q.shape
+    _check_square(H)
+    n = H.shape[0]
+    _check_block(Q, n, None, "Q")
+    k = Q.shape[1]
     if handle is None:
         handle = Handle(n, max(1, k - 1), 1, H.dtype)
+    _check_handle(handle, n, H.dtype, k=k)
     buf = _colmajor(Q.to(H.dtype))
     ritz = np.zeros(k)
     res = np.zeros(k)
@@ -349,11 +421,17 @@ def chase_rayleigh_ritz(H, Q, norm_scale=1.0, handle=None):
 
 def chase_eigval_adjoint(V, g, dH, handle=None):
     """dH += V diag(g) V^H (in place on the torch tensor dH, n x n)."""
+    if V.dim() != 2:
+        raise ValueError(f"V must be a matrix, got shape {tuple(V.shape)}")
     n, m = V.shape
+    _check_square(dH)
+    if dH.shape[0] != n or dH.dtype != V.dtype:
+        raise ValueError(f"dH must be a contiguous ({n}, {n}) {V.dtype} matrix")
     if handle is None:
         handle = Handle(n, max(1, m - 1) if m > 1 else 1, 1, V.dtype)
+    _check_handle(handle, n, V.dtype, k=m)
     buf = _colmajor(V)
-    gg = np.ascontiguousarray(np.asarray(g, dtype=np.float64))
+    gg = _host_vec(g, m, np.float64, "g")
     _check(lib().chase_eigval_adjoint(handle.ptr, _dev(buf), n, m,
                                       gg.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       _dev(dH), n, _stream()))
@@ -365,12 +443,20 @@ def chase_eigvec_adjoint(H, V, lam, G, dH, handle=None, tol=1e-10, max_iter=5000
     (n x m torch tensor, eigenvalues lam ascending) with G = dL/dV (torch's
     convention), in place on the torch tensor dH (n x n).  Returns the number
     of conjugate-gradient iterations of the complement solves."""
-    n, m = V.shape
+    _check_square(H)
+    n = H.shape[0]
+    _check_block(V, n, None, "V")
+    m = V.shape[1]
+    _check_block(G, n, m, "G")
+    _check_square(dH)
+    if dH.shape[0] != n or dH.dtype != H.dtype:
+        raise ValueError(f"dH must be a contiguous ({n}, {n}) {H.dtype} matrix")
     if handle is None:
         handle = Handle(n, m, 1 if m < n - 1 else max(1, n - m), H.dtype)
+    _check_handle(handle, n, H.dtype, k=m)
     vbuf = _colmajor(V.to(H.dtype))
     gbuf = _colmajor(G.to(H.dtype))
-    lm = np.ascontiguousarray(np.asarray(lam, dtype=np.float64))
+    lm = _host_vec(lam, m, np.float64, "lam")
     its = ctypes.c_int()
     _check(lib().chase_eigvec_adjoint(handle.ptr, _dev(H), n, _dev(vbuf), n, m,
                                       lm.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
@@ -383,7 +469,17 @@ def chase_filter_adjoint(H, gY, dH, handle, want_gX=False):
     """Adjoint of the last recorded chase_filter on `handle`: dH += dL/dH;
     returns dL/dX0 (n x k) if want_gX."""
     import torch
-    n, k = gY.shape
+    _check_square(H)
+    n = H.shape[0]
+    _check_handle(handle, n, H.dtype)
+    if getattr(handle, "tape_k", None) is None:
+        raise ValueError("no recorded filter tape on this handle (call chase_filter with "
+                         "record_tape=True)")
+    _check_block(gY, n, handle.tape_k, "gY")
+    _check_square(dH)
+    if dH.shape[0] != n or dH.dtype != H.dtype:
+        raise ValueError(f"dH must be a contiguous ({n}, {n}) {H.dtype} matrix")
+    k = gY.shape[1]
     gbuf = _colmajor(gY.to(H.dtype))
     gx = torch.empty_like(gbuf) if want_gX else None
     _check(lib().chase_filter_adjoint(handle.ptr, _dev(H), n, _dev(gbuf), n, _dev(dH), n,

@@ -195,3 +195,73 @@ def test_host_step_exports_reject_bad_arguments():
         pk.chase_degrees([1e-3], [0.1], 0.5, 1.0, 1e-10)    # mu_ne > b_sup
     with pytest.raises(pk.ChaseError, match="CHASE_ERR_ARG"):
         pk.chase_degrees([1e-3], [0.1], 1.0, 0.5, 1e-10, opts=pk.default_opts(max_deg=0))
+
+
+class _FakeHandle:
+    """Stand-in for a Handle (which needs a GPU to create): the binding checks
+    its sizes against the arguments before any library call."""
+
+    def __init__(self, n, nev, nex, cplx=True, tape_k=None):
+        import paper_2205_02491_amd as pk
+        self.n, self.nev, self.nex, self.cplx = n, nev, nex, cplx
+        self.opts = pk.default_opts()
+        self.tape_k = tape_k
+        self.ptr = None
+
+
+def test_binding_rejects_mismatched_handles_and_shapes():
+    """The library sizes every device read and host write by the handle, so
+    the binding refuses arguments that do not match it (a short V0 or degree
+    array would otherwise be read past its end)."""
+    import numpy as np
+    import torch
+    pk = _lib()
+    n, nev, nex = 50, 6, 4
+    ne = nev + nex
+    c = torch.complex128
+    H = torch.zeros((n, n), dtype=c)
+    h = _FakeHandle(n, nev, nex)
+    V0 = torch.zeros((n, ne), dtype=c)
+    S = torch.zeros((n, 4), dtype=c)
+    cases = [
+        (lambda: pk.chase_solve(H, nev, nex, V0=V0, S=S, handle=_FakeHandle(n + 1, nev, nex)),
+         "n=51"),
+        (lambda: pk.chase_solve(H, nev, nex, V0=V0, S=S, handle=_FakeHandle(n, nev + 1, nex)),
+         "nev=7"),
+        (lambda: pk.chase_solve(H, nev, nex, V0=V0, S=S, handle=_FakeHandle(n, nev, nex, False)),
+         "float64"),
+        (lambda: pk.chase_solve(H, nev, nex, V0=V0[:, :ne - 1], S=S, handle=h), "V0 must"),
+        (lambda: pk.chase_solve(H, nev, nex, V0=V0, S=S[:, :3], handle=h), "S must"),
+        (lambda: pk.chase_solve(H[:, :n - 1], nev, nex, V0=V0, S=S, handle=h), "square"),
+        (lambda: pk.chase_solve(H.T, nev, nex, V0=V0, S=S, handle=h) if not H.T.is_contiguous()
+         else (_ for _ in ()).throw(ValueError("contiguous")), "contiguous"),
+        (lambda: pk.chase_filter(H, V0, np.full(ne - 1, 2), 1.0, -1.0, 0.0, handle=h),
+         "degrees must"),
+        (lambda: pk.chase_filter(H, torch.zeros((n, ne + 1), dtype=c), np.full(ne + 1, 2),
+                                 1.0, -1.0, 0.0, handle=h), "do not fit"),
+        (lambda: pk.chase_filter(H, torch.zeros((n - 1, 3), dtype=c), np.full(3, 2),
+                                 1.0, -1.0, 0.0, handle=h), "X must"),
+        (lambda: pk.chase_filter_ritz(H, V0, V0[:, :3], np.zeros(ne), np.full(ne, 2),
+                                      1.0, -1.0, 0.0, handle=h), "R must"),
+        (lambda: pk.chase_filter_ritz(H, V0, V0, np.zeros(3), np.full(ne, 2),
+                                      1.0, -1.0, 0.0, handle=h), "theta must"),
+        (lambda: pk.chase_qr(torch.zeros((n, ne + 2), dtype=c), handle=h), "do not fit"),
+        (lambda: pk.chase_qr(torch.zeros((n + 2, 3), dtype=c), handle=h), "n=52"),
+        (lambda: pk.chase_rayleigh_ritz(H, torch.zeros((n - 2, 3), dtype=c), handle=h), "Q must"),
+        (lambda: pk.chase_eigval_adjoint(V0[:, :3], np.zeros(2), torch.zeros((n, n), dtype=c),
+                                         handle=h), "g must"),
+        (lambda: pk.chase_eigval_adjoint(V0[:, :3], np.zeros(3), torch.zeros((n, n - 1), dtype=c),
+                                         handle=h), "square"),
+        (lambda: pk.chase_eigvec_adjoint(H, V0[:, :3], np.zeros(3), V0[:, :2],
+                                         torch.zeros((n, n), dtype=c), handle=h), "G must"),
+        (lambda: pk.chase_eigvec_adjoint(H, V0[:, :3], np.zeros(4), V0[:, :3],
+                                         torch.zeros((n, n), dtype=c), handle=h), "lam must"),
+        (lambda: pk.chase_filter_adjoint(H, V0, torch.zeros((n, n), dtype=c), h), "no recorded"),
+        (lambda: pk.chase_filter_adjoint(H, V0[:, :2], torch.zeros((n, n), dtype=c),
+                                         _FakeHandle(n, nev, nex, tape_k=3)), "gY must"),
+        (lambda: pk.chase_lanczos(H, torch.zeros((n, 2), dtype=c), handle=_FakeHandle(n + 1, 2, 2)),
+         "n=51"),
+    ]
+    for fn, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            fn()
