@@ -162,4 +162,9 @@ int fp64_tail_steps(double floor, double lam_nev, double c, double e, double tol
   return (std::isfinite(j) && j < deg) ? (int)j : 0;
 }
 
+double low_precision_floor(bool split_bf16, int64_t n) {
+  if (split_bf16) return 0x1p-14;
+  return 0x1p-17 * std::sqrt(std::max(1.0, (double)n / 3000.0));
+}
+
 }  // namespace chase

@@ -37,4 +37,11 @@ int optimal_degree(double res, double ritz, double c, double e, double tol, cons
 // lam_nev is not below the damped interval or floor <= tol.
 int fp64_tail_steps(double floor, double lam_nev, double c, double e, double tol, int deg);
 
+// Relative rounding floor of a plain low-precision filter pass over an
+// n x n matrix, the `floor` of fp64_tail_steps: 2^-14 for split-BF16
+// products (set by the operands' 16-bit representation, independent of n);
+// 2^-17 sqrt(max(1, n/3000)) for FP32 products (set by the accumulation of
+// n-term sums, whose rounding grows like sqrt(n); calibrated at n = 3000).
+double low_precision_floor(bool split_bf16, int64_t n);
+
 }  // namespace chase

@@ -36,6 +36,8 @@ int shim_degree(double res, double ritz, double c, double e, double tol, int max
   return chase::optimal_degree(res, ritz, c, e, tol, o, deg);
 }
 
+double shim_floor(int split_bf16, long n) { return chase::low_precision_floor(split_bf16 != 0, n); }
+
 int shim_tail(double floor, double lam_nev, double c, double e, double tol, int deg) {
   return chase::fp64_tail_steps(floor, lam_nev, c, e, tol, deg);
 }

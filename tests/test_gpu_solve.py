@@ -150,6 +150,23 @@ def test_solve_rejects_nan(pk):
     assert e.value.status == pk.ERR_NUMERIC
 
 
+def test_solve_rejects_degree_beyond_the_coefficient_table(pk):
+    """degree is capped at min(max_deg + 1, 1000) on the host, before any
+    device work: with max_deg = 1000 a degree of 1001 would round up to 1002
+    steps, past the per-step coefficient table sized for 1000."""
+    announce("solve degree cap (host-side rejection)")
+    p = gen.make_uniform(n=200, nev=10, nex=6, cfg=14)
+    h = pk.Handle(p.n, p.nev, p.nex, opts=pk.default_opts(max_deg=1000))
+    try:
+        for bad in (1001, 1002):
+            with pytest.raises(pk.ChaseError) as e:
+                pk.chase_solve(to_gpu(p.H), p.nev, p.nex, p.tol, bad, to_gpu(p.V0),
+                               to_gpu(p.S), handle=h)
+            assert e.value.status == pk.ERR_ARG and "degree" in str(e.value)
+    finally:
+        h.close()
+
+
 def test_solve_warm_start_sequence(pk):
     """Sequences of correlated problems: the start block of the second solve
     is the first solve's eigenvectors plus nex seeded vectors.  The answer

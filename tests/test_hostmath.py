@@ -30,6 +30,8 @@ def shim(tmp_path_factory):
     lib.shim_degree.restype = ctypes.c_int
     lib.shim_tail.argtypes = [ctypes.c_double] * 5 + [ctypes.c_int]
     lib.shim_tail.restype = ctypes.c_int
+    lib.shim_floor.argtypes = [ctypes.c_int, ctypes.c_long]
+    lib.shim_floor.restype = ctypes.c_double
     return lib
 
 
@@ -158,3 +160,32 @@ def test_fp64_tail_rule(shim):
     assert shim.shim_tail(2.0 ** -14, lam_nev, c, e, 1e-10, 20) == 10
     assert shim.shim_tail(2.0 ** -17, lam_nev, c, e, 1e-10, 20) == 9
     assert shim.shim_tail(2.0 ** -14, lam_nev, c, e, 1e-10, 10) == 0
+
+
+def test_low_precision_floor(shim):
+    """Rounding floor of a plain low-precision pass: split BF16 2^-14 at every
+    n (the operands' 16-bit representation); FP32 2^-17 up to n=3000, the
+    calibration size, then growing like sqrt(n) (n-term accumulation)."""
+    for n in (1, 400, 3000, 20000, 100000):
+        assert shim.shim_floor(1, n) == 2.0 ** -14
+    for n in (1, 1000, 3000):
+        assert shim.shim_floor(0, n) == 2.0 ** -17
+    assert shim.shim_floor(0, 12000) == 2.0 ** -16
+    np.testing.assert_allclose(shim.shim_floor(0, 20000), 2.0 ** -17 * np.sqrt(20000 / 3000),
+                               rtol=1e-15)
+    # with the calibration problem's estimates (see test_fp64_tail_rule):
+    # the tail counted step by step, 9 at the calibration size and one or
+    # two steps more at n=100000 (floor 5.8x higher, rho = 4.05)
+    b_sup, mu_ne, lam_nev = 1.51457, 0.0074903, -0.857573
+    c, e = (b_sup + mu_ne) / 2, (b_sup - mu_ne) / 2
+    t = (lam_nev - c) / e
+    rho = abs(t) + np.sqrt(t * t - 1)
+    counted = {}
+    for n in (3000, 20000, 100000):
+        f = shim.shim_floor(0, n)
+        j = 1
+        while f / rho ** j > 1e-10:
+            j += 1
+        counted[n] = j
+        assert shim.shim_tail(f, lam_nev, c, e, 1e-10, 20) == j
+    assert counted[3000] == 9 and counted[100000] in (10, 11)
