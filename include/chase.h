@@ -213,9 +213,16 @@ chase_status chase_filter_ritz(chase_handle_t handle, const void* H_dev, int64_t
 /* QR step of Algorithm 1: orthonormalise the n x k block X_dev (ld ldx)
  * in place, keeping its first `locked` columns (assumed orthonormal)
  * unchanged; the others become orthonormal and orthogonal to them with the
- * same span as [locked | rest]. */
+ * same span as [locked | rest] (a span that contains it if the block is
+ * rank deficient).  Cholesky QR until two consecutive passes are clean;
+ * a pass whose factor is ill conditioned is redone on the shifted Gram
+ * matrix (at most 6 times); Householder QR (the paper's geqrf, Section 2.3)
+ * if the Gram matrix has a zero or non-finite diagonal entry or the
+ * shifted passes do not lead to clean ones.  shifted_passes and householder
+ * (may be NULL) receive the number of shifted passes and 1 if the
+ * Householder QR was used (else 0). */
 chase_status chase_qr(chase_handle_t handle, void* X_dev, int64_t ldx, int k,
-                      int locked, void* stream);
+                      int locked, int* shifted_passes, int* householder, void* stream);
 
 /* Rayleigh-Ritz + residual steps of Algorithm 1 on the orthonormal block
  * Q_dev (n x k, ld ldq, in/out): Q is replaced by the Ritz vectors,

@@ -721,12 +721,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
       fp64_tail = std::min(o.fp64_tail, deg0);
     } else if (o.fp64_tail < 0) {
       const double lam_nev = lanczos_bounds(lz_a, lz_b, o.lanczos_vecs, steps, n, nev, nullptr).mu_ne;
-      // floors calibrated at n = 3000: split BF16 is dominated by the
-      // operands' 16-bit representation; FP32 by the accumulation of its
-      // n-term sums, whose rounding grows like sqrt(n)
-      const double floor = pstart == PREC_BF16X3
-                               ? 0x1p-14
-                               : 0x1p-17 * std::sqrt(std::max(1.0, (double)n / 3000.0));
+      const double floor = low_precision_floor(pstart == PREC_BF16X3, n);
       fp64_tail = fp64_tail_steps(floor, lam_nev, 0.5 * (b_sup + mu_ne), 0.5 * (b_sup - mu_ne),
                                   tol, deg0);
     }
@@ -1115,7 +1110,8 @@ chase_status chase_solve(chase_handle_t h, const void* H, int64_t ldh, double to
     CHASE_REQUIRE(H && V0 && S && evals_host && evecs_dev, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldv >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(tol > 0 && std::isfinite(tol), "tol must be positive");
-    CHASE_REQUIRE(degree >= 2 && degree <= h->opts.max_deg + 1, "degree out of range");
+    CHASE_REQUIRE(degree >= 2 && degree <= std::min(h->opts.max_deg + 1, kMaxDegree),
+                  "degree out of range [2, min(max_deg + 1, 1000)]");
     hipStream_t st = static_cast<hipStream_t>(stream);
     set_stream(h, st);
     solve_impl(h, H, ldh, tol, degree, V0, S, evals_host, evecs_dev, ldv, resid_host, stats, st,
@@ -1226,7 +1222,8 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
   });
 }
 
-chase_status chase_qr(chase_handle_t h, void* X, int64_t ldx, int k, int locked, void* stream) {
+chase_status chase_qr(chase_handle_t h, void* X, int64_t ldx, int k, int locked,
+                      int* shifted_passes, int* householder, void* stream) {
   return guarded([&] {
     CHASE_REQUIRE(h != nullptr, "handle is NULL");
     CHASE_REQUIRE(X != nullptr, "NULL pointer argument");
@@ -1234,8 +1231,11 @@ chase_status chase_qr(chase_handle_t h, void* X, int64_t ldx, int k, int locked,
     CHASE_REQUIRE(k >= 1 && k <= h->ne && locked >= 0 && locked < k, "bad k / locked");
     hipStream_t st = static_cast<hipStream_t>(stream);
     set_stream(h, st);
-    qr_step(h, X, ldx, k, locked, h->W, nullptr, st);
+    chase_stats qs{};
+    qr_step(h, X, ldx, k, locked, h->W, &qs, st);
     CHASE_HIP(hipStreamSynchronize(st));
+    if (shifted_passes) *shifted_passes = qs.qr_shifted;
+    if (householder) *householder = qs.qr_householder;
   });
 }
 

@@ -95,27 +95,86 @@ def test_filter_ritz_defect_form_matches_oracle(pk, cplx):
         assert err < 1e-11, (a, deg[a], err)
 
 
-def test_filter_ritz_fp32_error_scales_with_residual(pk):
-    """FP32 products: the plain filter's error is ~u_32 relative to the output,
-    the defect form's is ~u_32 relative to the residual; for Ritz-like vectors
-    with residual ~1e-6 the latter must be orders of magnitude smaller."""
-    announce("filter_ritz FP32 error vs plain FP32")
+# Rounding model of a product computed from FP32 operands with FP32
+# accumulation (three real products per complex product): the error of one
+# column, H d, is at most C * u32 * sqrt(n) * ||H||_2 * ||d||_2 (the square-root
+# growth of n accumulated roundings of random sign; the operands' own rounding
+# adds u32 * ||H||_F / sqrt(n) * ||d||, below that), C = 1.  An error E_s made
+# at step s of the recurrence of Eq. (3) enters as alpha_s E_s and is carried
+# to the end by the same recurrence started from (x_{s-1}, x_s) = (0, 1), so
+# ||P_{s,m}(H)||_2 = max over the spectrum of |x_m(lambda)|.  The plain filter
+# multiplies X_{s-1} at steps 1..m; the defect form multiplies
+# D_{s-1} = X_{s-1} - T_{s-1}(theta) v at steps 2..m, whose norm is of the order
+# of the residual, so its bound (and error) scale with ||r|| instead of ||y||.
+FP32_PRODUCT_C = 1.0
+
+
+def _fp32_filter_bounds(h, lam, v, theta, m, b_sup, mu_1, mu_ne):
+    """Per-column bounds of the relative error (2-norm) of the plain and the
+    defect-form FP32 filter of degree m, from the model above; oracle FP64
+    values for the multiplied blocks."""
+    n = h.shape[0]
+    k = v.shape[1]
+    u32 = 2.0 ** -24
+    coef = oracle.filter_coefficients(m, b_sup, mu_1, mu_ne)
+    amp = np.zeros(m + 1)
+    for s in range(1, m + 1):
+        xp, xc = np.zeros_like(lam), np.ones_like(lam)
+        for j in range(s + 1, m + 1):
+            a, gmm, b = coef[j - 1]
+            xp, xc = xc, a * (lam - gmm) * xc + b * xp
+        amp[s] = np.max(np.abs(xc))
+    y, _ = oracle.chebyshev_filter(h, v, np.full(k, m), b_sup, mu_1, mu_ne)
+    ny = np.linalg.norm(y, axis=0)
+    hn = float(np.max(np.abs(lam)))
+    bp = np.zeros(k)
+    bd = np.zeros(k)
+    for s in range(1, m + 1):
+        if s == 1:
+            xs = v
+            ts = np.ones(k)
+        else:
+            xs, _ = oracle.chebyshev_filter(h, v, np.full(k, s - 1), b_sup, mu_1, mu_ne)
+            ts = oracle.cheb_poly_value(theta, s - 1, b_sup, mu_1, mu_ne)
+        w = abs(coef[s - 1][0]) * amp[s] * FP32_PRODUCT_C * u32 * math.sqrt(n) * hn
+        bp += w * np.linalg.norm(xs, axis=0)
+        if s >= 2:
+            bd += w * np.linalg.norm(xs - v * ts[None, :], axis=0)
+    return y, bp / ny, bd / ny
+
+
+def test_filter_ritz_fp32_error_bound(pk):
+    """FP32 products, plain filter vs defect-correction form on Ritz-like
+    vectors (residual ~1e-5): each column's error is below the bound of the
+    rounding model above, and the defect form's bound and error are orders of
+    magnitude below the plain filter's."""
+    announce("filter_ritz FP32 error vs the rounding-model bound")
     n, k = 900, 40
     h, lam, q, g = _problem(n, True, 2300)
     v = q[:, :k] + 1e-6 * gen.gaussian(g, (n, k), True)
     v /= np.linalg.norm(v, axis=0)[None, :]
     theta = np.real(np.sum(v.conj() * (h @ v), axis=0))
     r = h @ v - v * theta[None, :]
-    deg = np.full(k, 20, dtype=np.int32)
+    m = 20
+    deg = np.full(k, m, dtype=np.int32)
     b_sup, mu_1, mu_ne = 1.02, -1.0, lam[60]
-    y_ref, _ = oracle.chebyshev_filter(h, v, deg, b_sup, mu_1, mu_ne)
+    y_ref, bnd_p, bnd_d = _fp32_filter_bounds(h, lam, v, theta, m, b_sup, mu_1, mu_ne)
     y_d, _ = pk.chase_filter_ritz(to_gpu(h), to_gpu(v), to_gpu(r), theta, deg, b_sup, mu_1,
                                   mu_ne, prec=pk.PREC_FP32)
     y_p, _ = pk.chase_filter(to_gpu(h), to_gpu(v), deg, b_sup, mu_1, mu_ne, prec=pk.PREC_FP32)
-    e_d = rel_err(to_np(y_d), y_ref)
-    e_p = rel_err(to_np(y_p), y_ref)
-    assert e_p > 1e-8
-    assert e_d < 1e-9 and e_d < 1e-3 * e_p, (e_d, e_p)
+    ny = np.linalg.norm(y_ref, axis=0)
+    e_d = np.linalg.norm(to_np(y_d) - y_ref, axis=0) / ny
+    e_p = np.linalg.norm(to_np(y_p) - y_ref, axis=0) / ny
+    print(f"[fp32-model] plain: err max {e_p.max():.3e} bound min {bnd_p.min():.3e} "
+          f"ratio max {np.max(e_p / bnd_p):.3f} median {np.median(e_p / bnd_p):.3f}; "
+          f"defect: err max {e_d.max():.3e} bound max {bnd_d.max():.3e} "
+          f"ratio max {np.max(e_d / bnd_d):.3f} median {np.median(e_d / bnd_d):.3f}", flush=True)
+    assert np.all(e_p <= bnd_p), np.max(e_p / bnd_p)
+    assert np.all(e_d <= bnd_d), np.max(e_d / bnd_d)
+    # the two bounds differ only in the multiplied blocks' norms: ||D|| is
+    # of the order of the residual (here ~1e-5 of ||X||), times the growth
+    assert np.max(bnd_d) < 1e-2 * np.min(bnd_p)
+    assert np.max(e_d) < 1e-3 * np.max(e_p), (e_d.max(), e_p.max())
 
 
 # ------------------------------------------------------------------ split BF16
@@ -306,6 +365,59 @@ def test_qr_invariants_and_span(pk, n, k, locked, cplx):
     # same span: projector difference
     pdiff = qd @ qd.conj().T - q_ref @ q_ref.conj().T
     assert np.linalg.norm(pdiff, 2) < 1e-8
+
+
+@pytest.mark.parametrize("cplx,locked", [(True, 0), (True, 9), (False, 9)])
+def test_qr_householder_fallback_on_rank_deficient_block(pk, cplx, locked):
+    """The last resort of the QR step: a non-locked column that is exactly
+    zero (an exact linear combination of the others, with all coefficients
+    0) gives the Gram matrix a zero diagonal entry, which no Cholesky pass,
+    clean or shifted, can factor; the step then runs Householder QR (the
+    paper's geqrf) and copies the locked columns back.  The result is
+    orthonormal, keeps the locked columns bit for bit, contains span(X), and
+    spans the same space as the oracle's Householder QR over the columns
+    before the zero one (after it, a rank-deficient QR may complete the basis
+    with any orthonormal direction)."""
+    announce(f"qr Householder fallback cplx={cplx} locked={locked}")
+    n, k = 700, 60
+    g = np.random.Generator(np.random.PCG64(4242 + locked + cplx))
+    dt = complex if cplx else float
+    y = gen.haar(n, g, cplx)[:, :locked] if locked else np.zeros((n, 0), dt)
+    v = gen.gaussian(g, (n, k - locked), cplx)
+    jz = 23
+    v[:, jz] = 0.0
+    x = np.concatenate([y, v], axis=1)
+    qt, qs = pk.chase_qr(to_gpu(x), locked, return_stats=True)
+    qd = to_np(qt)
+    assert qs["householder"] == 1, qs
+    assert np.array_equal(qd[:, :locked], y)
+    assert np.linalg.norm(qd.conj().T @ qd - np.eye(k)) < 1e-12 * math.sqrt(k)
+    assert np.linalg.norm(x - qd @ (qd.conj().T @ x)) < 1e-12 * np.linalg.norm(x)
+    q_ref = oracle.qr_locked(y, v)
+    m = locked + jz
+    pdiff = qd[:, :m] @ qd[:, :m].conj().T - q_ref[:, :m] @ q_ref[:, :m].conj().T
+    assert np.linalg.norm(pdiff, 2) < 1e-12
+
+
+def test_qr_exactly_duplicated_columns(pk):
+    """Two exactly equal columns: rank deficient in exact arithmetic.  The QR
+    step (shifted Cholesky passes, or Householder if those do not lead to
+    clean ones) must still return an orthonormal basis that contains
+    span(X) and agrees with the oracle up to the duplicated column."""
+    announce("qr with exactly duplicated columns")
+    n, k = 700, 60
+    g = np.random.Generator(np.random.PCG64(4343))
+    x = gen.gaussian(g, (n, k), True)
+    x[:, 31] = x[:, 12]
+    qt, qs = pk.chase_qr(to_gpu(x), 0, return_stats=True)
+    qd = to_np(qt)
+    announce(f"  shifted passes {qs['shifted_passes']}, householder {qs['householder']}")
+    assert qs["shifted_passes"] > 0 or qs["householder"] == 1
+    assert np.linalg.norm(qd.conj().T @ qd - np.eye(k)) < 1e-12 * math.sqrt(k)
+    assert np.linalg.norm(x - qd @ (qd.conj().T @ x)) < 1e-10 * np.linalg.norm(x)
+    q_ref = oracle.qr_locked(np.zeros((n, 0), complex), x)
+    pdiff = qd[:, :31] @ qd[:, :31].conj().T - q_ref[:, :31] @ q_ref[:, :31].conj().T
+    assert np.linalg.norm(pdiff, 2) < 1e-10
 
 
 def test_single_vector_entry_points(pk):
