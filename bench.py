@@ -11,7 +11,11 @@ three terms, and the two-term split-BF16 mode).
 Prints one JSON line: the FP64 solve time as the value, the filter's
 algorithmic TFLOP/s against the FP64 MFMA peak (roofline), the Lanczos block
 GEMV's GB/s against the HBM peak, the mixed-precision solves on the same
-matrix, and the CPU oracle's filter rate on a bounded sample.
+matrix, the CPU oracle timed on the same host (its solve estimated from timed
+pieces of the same matrix, and a complete small solve beside the library's),
+and a second block on the mixed-precision workload: n=30000 complex128,
+lowest 2000 eigenvalues those of the (1-2-1) matrix of order 30000, the rest
+uniform up to 10, nev=1500, nex=500, solved once in each filter mode.
 """
 from __future__ import annotations
 
@@ -76,49 +80,130 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(H_host, V0_host, st, n, budget_s=20.0):
-    """Time the CPU oracle's filter (numpy FP64) on a bounded sample of the
-    same matrix: a block of columns of the start block at a fixed degree,
-    grown until it costs a few seconds, then extrapolated to the solve's
-    total filter work (the GPU run's Matvecs).  The extrapolation covers the
-    filter only, so it is a lower bound on the oracle's solve time."""
-    import numpy as np
+def host_info():
+    """CPU model, logical CPU count and BLAS thread pool of the host that runs
+    the oracle."""
     import threadpoolctl
+
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    blas = [{k: d.get(k) for k in ("internal_api", "num_threads", "version", "architecture")}
+            for d in threadpoolctl.threadpool_info() if d.get("user_api") == "blas"]
+    threads = max([b["num_threads"] or 1 for b in blas] or [1])
+    return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "blas": blas}, int(threads)
+
+
+def cpu_baseline(H_host, V0_host, S_host, st, n, ne, budget_s=12.0):
+    """The CPU oracle (numpy FP64) timed on the same matrix.  A full oracle
+    solve of this size takes minutes, so its pieces are timed once each and
+    added up as the solve runs them:
+    - filter: oracle.chebyshev_filter on column blocks of the start block at
+      degree 2, grown until the sample costs about budget_s, then scaled to
+      the GPU solve's matrix-vector products;
+    - Lanczos: a 3-step run from one start vector, scaled to the solve's
+      runs x steps products;
+    - QR, Rayleigh-Ritz and residual: one full-size call each
+      (oracle.qr_locked on the n x ne start block, oracle.rayleigh_ritz on the
+      result, oracle.residual_norms on the Ritz vectors), times the GPU solve's
+      iterations (exact for a one-iteration solve; later iterations of a
+      longer solve work on fewer active columns)."""
+    import numpy as np
 
     import oracle
 
-    info = threadpoolctl.threadpool_info()
-    threads = max([d.get("num_threads", 1) for d in info if d.get("user_api") == "blas"] or [1])
-    cols, deg = 32, 2
+    info, threads = host_info()
+    cols, deg = min(32, V0_host.shape[1]), 2
     spent = 0.0
-    rate = None
     total_mv = 0
     t_total = 0.0
     while spent < budget_s:
         x = V0_host[:, :cols]
-        degs = np.full(cols, deg)
+        degs = np.full(x.shape[1], deg)
         t0 = time.perf_counter()
         _, mv = oracle.chebyshev_filter(H_host, x, degs, st["b_sup"], st["mu_1"], st["mu_ne"])
         dt = time.perf_counter() - t0
         spent += dt
         total_mv += mv
         t_total += dt
-        rate = total_mv / t_total
         if dt * 3 > budget_s - spent:
             break
         cols = min(cols * 2, V0_host.shape[1])
+    rate = total_mv / t_total
     mv_full = st["matvecs_fp64"] + st["matvecs_low"]
+    t_filter = mv_full / rate
+    t0 = time.perf_counter()
+    oracle.lanczos_runs(H_host, S_host[:, :1], 3)
+    t_lz = (time.perf_counter() - t0) / 3 * 4 * 25
+    t0 = time.perf_counter()
+    q = oracle.qr_locked(V0_host[:, :0], V0_host[:, :ne])
+    t1 = time.perf_counter()
+    theta, va = oracle.rayleigh_ritz(H_host, q)
+    t2 = time.perf_counter()
+    oracle.residual_norms(H_host, va, theta, 1.0)
+    t3 = time.perf_counter()
+    t_iter = t3 - t0
+    it = st["iterations"]
+    est = t_lz + t_filter + it * t_iter
     flops_per_mv = 8.0 * n * n
     return {
-        "value": mv_full / rate,
-        "unit": "s (filter part of the solve, extrapolated)",
-        "cores": int(threads),
+        "value": est,
+        "unit": "s (oracle solve, estimated from timed pieces)",
+        "cores": threads,
         "kind": "oracle",
-        "sample": f"oracle.chebyshev_filter on the benchmark matrix, {total_mv} matrix-vector "
-                  f"products (column blocks of the start block, degree {deg}) in {t_total:.1f} s; "
-                  f"scaled to the GPU solve's {mv_full} Matvecs",
+        "sample": f"oracle pieces on the benchmark matrix: chebyshev_filter {total_mv} "
+                  f"matrix-vector products (column blocks of the start block, degree {deg}) in "
+                  f"{t_total:.1f} s, scaled to the GPU solve's {mv_full} Matvecs "
+                  f"({t_filter:.1f} s); Lanczos 3 steps scaled to 4 x 25 ({t_lz:.1f} s); one "
+                  f"full-size qr_locked + rayleigh_ritz + residual_norms ({t_iter:.1f} s) x "
+                  f"{it} iteration(s)",
         "filter_gflops": rate * flops_per_mv / 1e9,
+        "pieces_s": {"filter": t_filter, "lanczos": t_lz, "qr": t1 - t0, "rr": t2 - t1,
+                     "resid": t3 - t2},
+        "host": info,
     }
+
+
+def small_solve_pair(pk):
+    """The oracle's complete solve of the small workload (n=1000 complex128,
+    lambda i.i.d. uniform in [-1, 1], nev=100, nex=40, degree 20, tol 1e-10)
+    timed beside the library's solve of the same bytes (median of 5 after one
+    warm-up)."""
+    import numpy as np
+    import torch
+
+    import gen
+    import oracle
+
+    p = gen.make_uniform(n=1000, nev=100, nex=40)
+    t0 = time.perf_counter()
+    ev_o, _, _, st_o = oracle.solve(p.H, p.nev, p.nex, p.tol, p.deg, p.V0, p.S)
+    t_oracle = time.perf_counter() - t0
+    Hd = torch.from_numpy(p.H).cuda()
+    V0, S = torch.from_numpy(p.V0).cuda(), torch.from_numpy(p.S).cuda()
+    h = pk.Handle(p.H.shape[0], p.nev, p.nex, Hd.dtype, pk.default_opts())
+    ts = []
+    for k in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev, _, res, st = pk.chase_solve(Hd, p.nev, p.nex, p.tol, p.deg, V0, S, handle=h)
+        torch.cuda.synchronize()
+        if k:
+            ts.append(time.perf_counter() - t0)
+    h.close()
+    norm = max(abs(p.lam[0]), abs(p.lam[-1]))
+    return {"workload": "small (n=1000 c128, nev 100, nex 40)", "oracle_solve_s": t_oracle,
+            "oracle_iterations": st_o.iterations, "oracle_matvecs": st_o.matvecs,
+            "gpu_solve_s": float(np.median(ts)), "gpu_iterations": st["iterations"],
+            "gpu_matvecs": st["matvecs_fp64"] + st["matvecs_low"],
+            "max_eig_diff_rel": float(np.max(np.abs(ev - ev_o)) / norm),
+            "max_resid": float(res.max())}
 
 
 def independent_residual(H, vec, ev, prob):
@@ -311,6 +396,128 @@ def warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm, handle):
             "max_resid_warm_initial_rr": float(rr_res.max())}
 
 
+def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg=None,
+               warm_start=False):
+    """Time `steps` solves (after `warmup` untimed ones) of the problem in
+    each filter mode, one handle per mode; returns per-mode results."""
+    import numpy as np
+    import torch
+
+    n, nev, nex = wl["n"], wl["nev"], wl["nex"]
+    H, V0, S = prob["H"].contiguous(), prob["V0"], prob["S"]
+    lam = prob["lam"]
+    norm = max(abs(lam[0]), abs(lam[-1]))
+    results = {}
+    for prec in precs:
+        opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if verbose else 0)
+        if max_deg is not None:
+            opts.max_deg = max_deg
+        handle = pk.Handle(n, nev, nex, H.dtype, opts)
+        for w in range(warmup):
+            ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
+                                              handle=handle)
+            log(f"{label} {prec} warmup {w}: {st['t_all']:.2f} s, {st['iterations']} it")
+        torch.cuda.synchronize()
+        times, stats = [], []
+        t_start = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
+                                              handle=handle)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - ts)
+            stats.append(st)
+            log(f"{label} {prec} step {k}: {times[-1]:.2f} s, it={st['iterations']} "
+                f"mv64={st['matvecs_fp64']} mvlow={st['matvecs_low']} "
+                f"filter {st['filter_flops'] / st['t_filter_kernels'] / 1e12:.1f} TF")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        err = float(np.max(np.abs(ev - lam[:nev])))
+        indep = independent_residual(H, vec, ev, prob) / norm
+        # the filter launches of this mode's precision (a mixed solve also
+        # runs FP64 filter steps: the start block's FP64 tail, FP64 ranks)
+        per_mv = (8.0 if H.is_complex() else 2.0) * n * n
+        if prec == "fp64":
+            fl = sum(s["filter_flops"] for s in stats)
+            kt = sum(s["t_filter_kernels"] for s in stats)
+            launches = sum(s["filter_launches"] for s in stats)
+        else:
+            fl = per_mv * sum(s["matvecs_low"] for s in stats)
+            kt = sum(s["t_filter_kernels_low"] for s in stats)
+            launches = sum(s["filter_launches_low"] for s in stats)
+        lz_b = sum(s["lanczos_gemv_bytes"] for s in stats)
+        lz_t = sum(s["t_lanczos_gemv"] for s in stats)
+        results[prec] = dict(
+            lanczos_gemv_gbs=lz_b / lz_t / 1e9 if lz_t > 0 else None,
+            lanczos_gemv_ms=lz_t / max(1, sum(s["lanczos_gemv_launches"] for s in stats)) * 1e3,
+            solve_s=elapsed / steps, converged=bool(st["converged"]),
+            max_resid=float(res.max()), max_eig_err_rel=err / norm,
+            max_resid_independent=indep,
+            iterations=st["iterations"], matvecs_fp64=st["matvecs_fp64"],
+            matvecs_low=st["matvecs_low"], fp64_tail=st["fp64_tail"],
+            exec_per_algo=exec_per_algo(prec, st, wl["deg"], nev + nex),
+            filter_tflops=fl / kt / 1e12, filter_kernel_s=kt / steps,
+            filter_launches=launches // steps,
+            avg_launch_ms=kt / launches * 1e3, flops_per_launch=fl / launches,
+            phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")},
+            qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
+            stats=st, evals=ev)
+        if warm_start:
+            results[prec]["warm_start"] = warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm,
+                                                          handle)
+            log(f"{label} {prec} warm start: {results[prec]['warm_start']}")
+        del vec
+        handle.close()
+    return results
+
+
+MODE_KEYS = ("solve_s", "converged", "max_resid", "max_eig_err_rel", "max_resid_independent",
+             "iterations", "matvecs_fp64", "matvecs_low", "fp64_tail", "filter_tflops", "phases",
+             "qr_shifted", "qr_householder")
+
+
+def mode_summary(m, prec, fp64_solve_s):
+    out = {k: m[k] for k in MODE_KEYS}
+    out["filter_frac_peak"] = m["filter_tflops"] / PEAK_TFLOPS[prec]
+    out["filter_executed_frac"] = m["exec_per_algo"] * m["filter_tflops"] / PEAK_TFLOPS[prec]
+    out["avg_launch_ms"] = m["avg_launch_ms"]
+    if fp64_solve_s is not None and prec != "fp64":
+        out["speedup_vs_fp64"] = fp64_solve_s / m["solve_s"]
+    return out
+
+
+def mixed_workload_block(pk, precs, steps, warmup):
+    """FP64 versus mixed-precision solves on the n=30000 workload (lowest 2000
+    eigenvalues those of the (1-2-1) matrix, the rest uniform up to 10;
+    nev=1500, nex=500): every mode solves the same matrix; the FP64 one is the
+    reference for the speedups and the eigenvalue differences."""
+    import numpy as np
+    import torch
+
+    import gen
+
+    wl = WORKLOADS["cluster121_30k"]
+    t0 = time.perf_counter()
+    prob = gen.make_torch(wl["kind"], wl["n"], wl["nev"], wl["nex"], device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"generated cluster121_30k n={wl['n']} in {time.perf_counter() - t0:.1f} s")
+    res = time_modes(pk, prob, wl, precs, steps, warmup, "cluster121_30k")
+    lam = prob["lam"]
+    norm = max(abs(lam[0]), abs(lam[-1]))
+    fp64_s = res["fp64"]["solve_s"] if "fp64" in res else None
+    out = {"workload": "cluster121_30k", "n": wl["n"], "nev": wl["nev"], "nex": wl["nex"],
+           "degree": wl["deg"], "tol": wl["tol"], "steps": steps, "warmup": warmup}
+    for prec in precs:
+        out[prec] = mode_summary(res[prec], prec, fp64_s)
+        if "fp64" in res and prec != "fp64":
+            out[prec]["max_eig_diff_vs_fp64_rel"] = float(
+                np.max(np.abs(res[prec]["evals"] - res["fp64"]["evals"])) / norm)
+    del prob
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -321,6 +528,12 @@ def main():
                     choices=["fp64", "fp32", "bf16x3", "bf16x2", "both", "all"],
                     help="filter modes to time: both = fp64 + fp32, all = fp64 + fp32 + bf16x3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed-workload", action="store_true",
+                    help="skip the n=30000 FP64-versus-mixed block of the default workload")
+    ap.add_argument("--mixed-steps", type=int, default=1,
+                    help="timed solves per mode in the n=30000 block")
+    ap.add_argument("--mixed-warmup", type=int, default=0,
+                    help="untimed solves per mode in the n=30000 block")
     ap.add_argument("--warm-start", action="store_true",
                     help="also time a sequence step: H + E (||E||_2 = 1e-5 ||H||_2, seeded "
                          "Hermitian) solved cold and warm-started from the previous "
@@ -350,7 +563,6 @@ def main():
               "(run with --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import gen
@@ -377,72 +589,12 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     log(f"generated {args.workload} n={n} in {time.perf_counter() - t0:.1f} s")
-    H, V0, S = prob["H"].contiguous(), prob["V0"], prob["S"]
-    lam = prob["lam"]
-    norm = max(abs(lam[0]), abs(lam[-1]))
 
     precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"]}.get(args.prec,
                                                                           [args.prec])
-    results = {}
-    for prec in precs:
-        opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if args.verbose else 0)
-        if args.max_deg is not None:
-            opts.max_deg = args.max_deg
-        handle = pk.Handle(n, nev, nex, H.dtype, opts)
-        for w in range(args.warmup):
-            ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
-                                              handle=handle)
-            log(f"{prec} warmup {w}: {st['t_all']:.2f} s, {st['iterations']} it")
-        torch.cuda.synchronize()
-        times, stats = [], []
-        t_start = time.perf_counter()
-        for k in range(args.steps):
-            ts = time.perf_counter()
-            ev, vec, res, st = pk.chase_solve(H, nev, nex, wl["tol"], wl["deg"], V0, S,
-                                              handle=handle)
-            torch.cuda.synchronize()
-            times.append(time.perf_counter() - ts)
-            stats.append(st)
-            log(f"{prec} step {k}: {times[-1]:.2f} s, it={st['iterations']} "
-                f"mv64={st['matvecs_fp64']} mvlow={st['matvecs_low']} "
-                f"filter {st['filter_flops'] / st['t_filter_kernels'] / 1e12:.1f} TF")
-        torch.cuda.synchronize()
-        elapsed = time.perf_counter() - t_start
-        err = float(np.max(np.abs(ev - lam[:nev])))
-        indep = independent_residual(H, vec, ev, prob) / norm
-        # the filter launches of this mode's precision (a mixed solve also
-        # runs FP64 filter steps: the start block's FP64 tail, FP64 ranks)
-        per_mv = (8.0 if H.is_complex() else 2.0) * n * n
-        if prec == "fp64":
-            fl = sum(s["filter_flops"] for s in stats)
-            kt = sum(s["t_filter_kernels"] for s in stats)
-            launches = sum(s["filter_launches"] for s in stats)
-        else:
-            fl = per_mv * sum(s["matvecs_low"] for s in stats)
-            kt = sum(s["t_filter_kernels_low"] for s in stats)
-            launches = sum(s["filter_launches_low"] for s in stats)
-        lz_b = sum(s["lanczos_gemv_bytes"] for s in stats)
-        lz_t = sum(s["t_lanczos_gemv"] for s in stats)
-        results[prec] = dict(
-            lanczos_gemv_gbs=lz_b / lz_t / 1e9 if lz_t > 0 else None,
-            lanczos_gemv_ms=lz_t / max(1, sum(s["lanczos_gemv_launches"] for s in stats)) * 1e3,
-            solve_s=elapsed / args.steps, converged=bool(st["converged"]),
-            max_resid=float(res.max()), max_eig_err_rel=err / norm,
-            max_resid_independent=indep,
-            iterations=st["iterations"], matvecs_fp64=st["matvecs_fp64"],
-            matvecs_low=st["matvecs_low"], fp64_tail=st["fp64_tail"],
-            exec_per_algo=exec_per_algo(prec, st, wl["deg"], nev + nex),
-            filter_tflops=fl / kt / 1e12, filter_kernel_s=kt / args.steps,
-            filter_launches=launches // args.steps,
-            avg_launch_ms=kt / launches * 1e3, flops_per_launch=fl / launches,
-            phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")},
-            qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
-            stats=st)
-        if args.warm_start:
-            results[prec]["warm_start"] = warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm,
-                                                          handle)
-            log(f"{prec} warm start: {results[prec]['warm_start']}")
-        handle.close()
+    results = time_modes(pk, prob, wl, precs, args.steps, args.warmup, args.workload,
+                         verbose=args.verbose, max_deg=args.max_deg, warm_start=args.warm_start)
+    H = prob["H"]
 
     main_prec = "fp64" if "fp64" in results else precs[0]
     r = results[main_prec]
@@ -495,24 +647,26 @@ def main():
     for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3"), ("bf16x2", "mixed_bf16x2")):
         if low not in results or main_prec == low:
             continue
-        m = results[low]
-        out[key] = {k: m[k] for k in ("solve_s", "converged", "max_resid", "max_eig_err_rel",
-                                      "max_resid_independent",
-                                      "iterations", "matvecs_fp64", "matvecs_low",
-                                      "fp64_tail", "filter_tflops", "phases", "qr_shifted",
-                                      "qr_householder")}
-        out[key]["filter_frac_peak"] = m["filter_tflops"] / PEAK_TFLOPS[low]
-        out[key]["filter_executed_frac"] = m["exec_per_algo"] * m["filter_tflops"] / \
-            PEAK_TFLOPS[low]
-        out[key]["speedup_vs_fp64"] = r["solve_s"] / m["solve_s"]
+        out[key] = mode_summary(results[low], low, r["solve_s"])
     if args.warm_start:
         out["warm_start"] = {p: results[p]["warm_start"] for p in results}
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         Hh = H.cpu().numpy()
-        V0h = V0.cpu().numpy()
-        out["cpu_baseline"] = cpu_baseline(Hh, V0h, r["stats"], n)
-        log(f"cpu baseline done in {time.perf_counter() - t0:.1f} s")
+        V0h = prob["V0"].cpu().numpy()
+        Sh = prob["S"].cpu().numpy()
+        out["cpu_baseline"] = cpu_baseline(Hh, V0h, Sh, r["stats"], n, nev + nex)
+        del Hh, V0h, Sh
+        out["cpu_baseline"]["small_solve"] = small_solve_pair(pk)
+        log(f"cpu baseline done in {time.perf_counter() - t0:.1f} s: "
+            f"{out['cpu_baseline']['pieces_s']}, small {out['cpu_baseline']['small_solve']}")
+    del H, prob, results
+    torch.cuda.empty_cache()
+    if args.workload == "geometric20k" and not (args.no_mixed_workload or args.gen_elementary):
+        # the metric's FP64-versus-mixed comparison on the workload where the
+        # mixed-precision policy does its work (many iterations, defect form)
+        out["mixed_workload"] = mixed_workload_block(
+            pk, ["fp64", "fp32", "bf16x3", "bf16x2"], args.mixed_steps, args.mixed_warmup)
     print(json.dumps(out), flush=True)
 
 

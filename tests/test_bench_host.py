@@ -35,3 +35,31 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode != 0
     assert "one GPU" in r.stderr or "1 GPU" in r.stderr or "--gpus 1" in r.stderr
+
+
+def test_mode_summary_fractions_and_speedup():
+    m = {k: 0 for k in bench.MODE_KEYS}
+    m.update(solve_s=2.0, filter_tflops=500.0, exec_per_algo=2.5, avg_launch_ms=20.0)
+    out = bench.mode_summary(m, "bf16x2", 10.0)
+    assert abs(out["filter_frac_peak"] - 0.2) < 1e-15
+    assert abs(out["filter_executed_frac"] - 0.5) < 1e-15
+    assert abs(out["speedup_vs_fp64"] - 5.0) < 1e-15
+    assert "speedup_vs_fp64" not in bench.mode_summary(dict(m, exec_per_algo=0.75), "fp64", 10.0)
+
+
+def test_cpu_baseline_pieces_on_a_small_matrix():
+    # the CPU leg runs the oracle's pieces on the benchmark matrix; on a small
+    # one it must finish and add them up as documented
+    import numpy as np
+
+    import gen
+    p = gen.make_uniform(n=300, nev=20, nex=10)
+    st = {"b_sup": 1.2, "mu_1": -1.0, "mu_ne": -0.5, "matvecs_fp64": 600, "matvecs_low": 0,
+          "iterations": 2}
+    cb = bench.cpu_baseline(p.H, p.V0, p.S, st, 300, 30, budget_s=0.05)
+    pc = cb["pieces_s"]
+    est = pc["lanczos"] + pc["filter"] + 2 * (pc["qr"] + pc["rr"] + pc["resid"])
+    assert abs(cb["value"] - est) <= 1e-9 * est
+    assert cb["kind"] == "oracle" and cb["cores"] >= 1
+    assert cb["host"]["os_cpu_count"] == os.cpu_count()
+    assert np.isfinite(cb["filter_gflops"])
