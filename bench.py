@@ -459,7 +459,8 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
             filter_tflops=fl / kt / 1e12, filter_kernel_s=kt / steps,
             filter_launches=launches // steps,
             avg_launch_ms=kt / launches * 1e3, flops_per_launch=fl / launches,
-            phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_resid")},
+            phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_rr_eig",
+                                       "t_resid")},
             qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
             stats=st, evals=ev)
         if warm_start:

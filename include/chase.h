@@ -104,7 +104,21 @@ typedef struct chase_opts {
                           estimate of the nev-th eigenvalue, used only if
                           fewer than the degree; 0: off; > 0: that many
                           (capped at the degree).  Ignored with initial_rr  */
-  int reserved[5];
+  int seed;            /* start blocks the caller leaves NULL in chase_solve
+                          (V0_dev, S_dev) are drawn from N(0, 1) by a
+                          counter-based generator (SplitMix64 + Box-Muller)
+                          with this seed: the same seed gives the same
+                          blocks on every call and device (default 0)      */
+  int debug;           /* 1 (or the environment variable CHASE_DEBUG=1 when
+                          the handle is created): chase_solve checks that H
+                          is Hermitian (max |H - H^H| <= 1e-12 max |H|,
+                          else CHASE_ERR_ARG), the block after every QR step
+                          (max |Q^H Q - I| <= 1e-8, else CHASE_ERR_NUMERIC)
+                          and every phase's output for NaN/Inf; the measured
+                          defects go to chase_stats.  Costs one extra pass
+                          over H and one Gram product per iteration
+                          (default 0)                                       */
+  int reserved[3];
 } chase_opts;
 
 typedef struct chase_stats {
@@ -128,6 +142,11 @@ typedef struct chase_stats {
   int64_t filter_launches_low; /* the low-precision ones of filter_launches */
   int fp64_tail;           /* FP64 steps at the end of the start block's
                               low-precision pass (0: none)                  */
+  double debug_herm_defect; /* debug mode: max |H - H^H| / max |H| (else 0)  */
+  double debug_orth_defect; /* debug mode: largest max |Q^H Q - I| after a QR
+                               step of the solve (else 0)                   */
+  double t_rr_eig;         /* summed HIP-event time of the dense eigensolves
+                              of Rayleigh-Ritz (part of t_rr)               */
 } chase_stats;
 
 typedef struct chase_handle_s* chase_handle_t;
@@ -159,7 +178,8 @@ void chase_destroy(chase_handle_t handle);
  * ||H v - lambda v||_2 relative to the largest Lanczos Ritz value in
  * magnitude, a lower bound of ||H||_2), degree >= 2
  * (initial degree, rounded up to even), V0_dev (n x (nev+nex), ld n: the
- * start block), S_dev (n x lanczos_vecs, ld n: Lanczos start vectors).
+ * start block; NULL: drawn by the library, see chase_opts.seed), S_dev
+ * (n x lanczos_vecs, ld n: Lanczos start vectors; NULL: drawn likewise).
  * Outputs: evals_host[nev] ascending, evecs_dev (n x nev, ld ldv),
  * resid_host[nev] (may be NULL), stats (may be NULL).
  * CHASE_ERR_NOCONV: max_iter reached; outputs hold the lowest nev current

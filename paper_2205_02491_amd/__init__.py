@@ -45,7 +45,8 @@ class Opts(ctypes.Structure):
                 ("lanczos_vecs", ctypes.c_int), ("max_iter", ctypes.c_int),
                 ("filter_prec", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
-                ("fp64_tail", ctypes.c_int), ("reserved", ctypes.c_int * 5)]
+                ("fp64_tail", ctypes.c_int), ("seed", ctypes.c_int),
+                ("debug", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -61,7 +62,9 @@ class Stats(ctypes.Structure):
                 ("t_lanczos_gemv", ctypes.c_double), ("lanczos_gemv_launches", ctypes.c_int64),
                 ("lanczos_gemv_bytes", ctypes.c_double),
                 ("t_filter_kernels_low", ctypes.c_double),
-                ("filter_launches_low", ctypes.c_int64), ("fp64_tail", ctypes.c_int)]
+                ("filter_launches_low", ctypes.c_int64), ("fp64_tail", ctypes.c_int),
+                ("debug_herm_defect", ctypes.c_double),
+                ("debug_orth_defect", ctypes.c_double), ("t_rr_eig", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -258,12 +261,11 @@ def _ensure_handle(handle, H, nev, nex, opts):
     return Handle(H.shape[0], nev, nex, H.dtype, opts), True
 
 
-def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, handle=None,
-                seed=0):
+def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, handle=None):
     """Lowest nev eigenpairs of the Hermitian H (n x n torch tensor on the GPU,
     complex128 or float64).  V0 (n x (nev+nex)) and S (n x lanczos_vecs) are
-    the start block and the Lanczos start vectors (drawn from a seeded normal
-    distribution when omitted).  Returns (evals numpy[nev], evecs tensor
+    the start block and the Lanczos start vectors; when omitted the library
+    draws them (seeded by opts.seed).  Returns (evals numpy[nev], evecs tensor
     (n, nev), resid numpy[nev], stats dict).  NOCONV returns the best pairs
     with stats['converged'] = False."""
     import torch
@@ -279,21 +281,16 @@ def chase_solve(H, nev, nex, tol=1e-10, degree=20, V0=None, S=None, opts=None, h
             _check_block(V0, n, ne, "V0")
         if S is not None:
             _check_block(S, n, nl, "S")
-        if V0 is None or S is None:
-            g = torch.Generator(device=H.device)
-            g.manual_seed(seed)
-            if V0 is None:
-                V0 = torch.randn((n, ne), generator=g, dtype=H.dtype, device=H.device)
-            if S is None:
-                S = torch.randn((n, nl), generator=g, dtype=H.dtype, device=H.device)
-        v0c = _colmajor(V0.to(H.dtype))
-        sc = _colmajor(S.to(H.dtype))
+        v0c = None if V0 is None else _colmajor(V0.to(H.dtype))
+        sc = None if S is None else _colmajor(S.to(H.dtype))
         evecs_buf = torch.empty((nev, n), dtype=H.dtype, device=H.device)
         ev = np.zeros(nev)
         rs = np.zeros(nev)
         st = Stats()
-        status = lib().chase_solve(h.ptr, _dev(H), n, float(tol), int(degree), _dev(v0c),
-                                   _dev(sc), ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+        status = lib().chase_solve(h.ptr, _dev(H), n, float(tol), int(degree),
+                                   None if v0c is None else _dev(v0c),
+                                   None if sc is None else _dev(sc),
+                                   ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    _dev(evecs_buf), n,
                                    rs.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                    ctypes.byref(st), _stream())

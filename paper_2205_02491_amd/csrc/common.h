@@ -106,7 +106,7 @@ struct GemmArgs {
 // S8_KPAD and grouped by 8; group g of column c at byte (c*groups + g)*planes*16
 // holding re_hi[8] re_lo[8] im_hi[8] im_lo[8] (real: hi[8] lo[8]),
 // hi = bf16(x), lo = bf16(x - hi), round to nearest even.
-constexpr int S8_KPAD = 16;
+constexpr int S8_KPAD = 32;  // the two-term kernel's K chunk
 constexpr int S8_COLS_A = 256;  // row tile of the split-BF16 GEMM
 constexpr int S8_COLS_B = 128;  // column tile of the split-BF16 GEMM
 inline int64_t s8_groups(int64_t K) { return (K + S8_KPAD - 1) / S8_KPAD * (S8_KPAD / 8); }
@@ -185,6 +185,14 @@ void to_f32(bool cplx, const void* src, int64_t lds, void* dst, int64_t n, hipSt
 void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, int* flags,
                   hipStream_t st);
 
+// Seeded N(0, 1) draws into an n x k block (ld ldx; complex: re and im each
+// N(0, 1)) from a counter-based generator, reproducible for (seed, stream_id).
+void fill_gaussian(bool cplx, void* X, int64_t ldx, int64_t n, int64_t k, uint64_t seed,
+                   uint64_t stream_id, hipStream_t st);
+// Debug checks of an n x n matrix: out2[0] = max |A - A^H| (mode 0) or
+// max |A - I| (mode 1), out2[1] = max |A| (device doubles).
+void max_defect(bool cplx, const void* A, int64_t lda, int64_t n, int mode, double* out2,
+                hipStream_t st);
 // Batched conjugate gradients (one system per column of an n x k block):
 // out[j] = Re(x_j^H y_j)
 void col_dots(bool cplx, const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t n,

@@ -60,6 +60,7 @@
 // reaches 94% of peak, and the kernel without its global loads 82%.
 #include <algorithm>
 #include <atomic>
+#include <cstdlib>
 
 #include "common.h"
 
@@ -74,7 +75,7 @@ typedef unsigned int u4v __attribute__((ext_vector_type(4)));
 constexpr int TBM = S8_COLS_A;  // rows of C per workgroup (columns of the T split)
 constexpr int TBN = S8_COLS_B;  // columns of C per workgroup (columns of the X split)
 constexpr int NTHR = 512;
-constexpr int KC = S8_KPAD;     // K per chunk = one MFMA k-step
+constexpr int KC = 16;          // K per chunk = one MFMA k-step
 constexpr int NSTAGE = 2;       // LDS stages (stage of chunk c: c & 1)
 
 __device__ inline bf8 as_bf8(u4v v) { return __builtin_bit_cast(bf8, v); }
@@ -348,6 +349,165 @@ __global__ __launch_bounds__(NTHR) void gemm_bf16x3_kernel(GemmArgs g, int tiles
     epilogue<CPLX>(g, acc_re, acc_im, i0, j0, wi, wj, l32, h);
 }
 
+// Two-term products with a 32-deep K chunk per barrier.  The block operand
+// enters the two-term products through its hi planes only, so only those are
+// copied to LDS: a chunk takes 256 x 256 B of T and 128 x 128 B of the block
+// (complex), 80 KB, and two stages fill the CU's 160 KB.  Per barrier a wave
+// issues 64 MFMAs (twice the 16-deep kernel's), and a chunk's copies are
+// issued a whole chunk (two MFMA k-steps) before they are needed.  T columns
+// are 256 B (one row of the 64 banks): piece p of column c sits in slot
+// p ^ (c & 15); the block's 128-B columns use p ^ ((c >> 1) & 7).  Requires
+// s8_groups to be a multiple of 4 (K padded to 32).
+constexpr int KC2 = 32;
+
+template <int CB, int PIECES>
+__device__ inline int lds_slot(int c, int p) {
+  constexpr int R = 256 / CB;  // columns per 256-byte row of the banks
+  return p ^ ((c / R) & (PIECES - 1));
+}
+
+template <bool CPLX, bool SPLIT>
+__global__ __launch_bounds__(NTHR) void gemm_bf16x2_k32_kernel(GemmArgs g, int tiles_n,
+                                                               int ntiles, TailPlan tp) {
+  constexpr int P = CPLX ? 4 : 2;   // planes of a group in the s8 layout
+  constexpr int PX = P / 2;         // the block's hi planes (re_hi, im_hi)
+  constexpr int GPC = KC2 / 8;      // 8-row groups per chunk
+  constexpr int CBT = GPC * P * 16;   // bytes of a T column per chunk
+  constexpr int CBX = GPC * PX * 16;  // bytes of a block column per chunk (hi planes)
+  constexpr int PT = CBT / 16, PXN = CBX / 16;
+  constexpr int NW = NTHR / 64;
+  constexpr int TBYTES = TBM * CBT;
+  constexpr int STAGE = TBYTES + TBN * CBX;
+  constexpr int TBLK = TBYTES / 1024, XBLK = TBN * CBX / 1024;
+  constexpr int LOADS = (TBLK + XBLK) / NW;
+  constexpr int WGI = TBM / 64;
+  static_assert(WGI * (TBN / 64) == NW, "64 x 64 per wave");
+  static_assert(LOADS * NW == TBLK + XBLK && LOADS <= 15, "chunk / waves, vmcnt immediate");
+  static_assert(2 * STAGE <= 160 * 1024, "two stages in the CU's LDS");
+  __shared__ __attribute__((aligned(1024))) char lds[2 * STAGE];
+
+  const int per_xcd = gridDim.x >> 3;
+  const int u = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+  if (u >= (SPLIT ? tp.rem * tp.slices : ntiles)) return;
+  const int slice = SPLIT ? u / tp.rem : 0;
+  const int tr = SPLIT ? u - slice * tp.rem : 0;
+  const int t = SPLIT ? tp.tile0 + tr : u;
+  const int tm = t / tiles_n, tn = t - tm * tiles_n;
+  const int64_t i0 = (int64_t)tm * TBM, j0 = (int64_t)tn * TBN;
+  const int64_t colbytes = g.s8_groups * P * 16;
+  const char* __restrict__ Ta = static_cast<const char*>(g.a_s8) + i0 * colbytes;
+  const char* __restrict__ Xb = static_cast<const char*>(g.b_s8) + j0 * colbytes;
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave % WGI, wj = wave / WGI;
+  const int l32 = lane & 31, h = lane >> 5;
+
+  // Each wave-wide direct load fills 1 KB of the stage: T blocks first (1024
+  // / CBT columns each), then the block's (1024 / CBX columns).  A lane
+  // fetches the piece whose slot in its column is its position in the
+  // column's stretch (lds_slot is an involution in p).
+  auto issue = [&](int64_t c) {
+    char* base = lds + (int)(c & 1) * STAGE;
+#pragma unroll
+    for (int e = 0; e < LOADS; ++e) {
+      const int blk = wave * LOADS + e;
+      const char* src;
+      if (blk < TBLK) {
+        const int col = blk * (1024 / CBT) + lane / PT;
+        const int pc = lds_slot<CBT, PT>(col, lane % PT);
+        src = Ta + (int64_t)col * colbytes + c * (GPC * P * 16) + pc * 16;
+      } else {
+        const int col = (blk - TBLK) * (1024 / CBX) + lane / PXN;
+        const int pc = lds_slot<CBX, PXN>(col, lane % PXN);
+        const int gq = pc / PX, q = pc - gq * PX;
+        src = Xb + (int64_t)col * colbytes + c * (GPC * P * 16) + (gq * P + 2 * q) * 16;
+      }
+      __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                       (__attribute__((address_space(3))) void*)(base + blk * 1024),
+                                       16, 0, 0);
+    }
+  };
+
+  f16v acc_re[2][2], acc_im[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      acc_re[a][b] = f16v{};
+      acc_im[a][b] = f16v{};
+    }
+
+  const int64_t nchunks = g.s8_groups / GPC;
+  const int64_t cb = SPLIT ? slice * tp.cps : 0;
+  const int64_t ce = SPLIT ? (cb + tp.cps < nchunks ? cb + tp.cps : nchunks) : nchunks;
+  issue(cb);
+  for (int64_t c = cb; c < ce; ++c) {
+    // as in the 16-deep kernel: chunk c has landed, every wave is done with
+    // chunk c-1's stage, which chunk c+1 then fills
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0x70);  // vmcnt(0) lgkmcnt(0)
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (c + 1 < ce) issue(c + 1);
+    const char* st = lds + (int)(c & 1) * STAGE;
+    const char* stx = st + TBYTES;
+#pragma unroll
+    for (int s = 0; s < KC2 / 16; ++s) {
+      const int gq = 2 * s + h;  // the lane's 8-row group within the chunk
+      u4v tf[2][P], xf[2][PX];
+#pragma unroll
+      for (int f = 0; f < 2; ++f) {
+        const int ct = wi * 64 + f * 32 + l32;
+        const int cx = wj * 64 + f * 32 + l32;
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+          tf[f][p] = *reinterpret_cast<const u4v*>(st + ct * CBT +
+                                                   lds_slot<CBT, PT>(ct, gq * P + p) * 16);
+#pragma unroll
+        for (int q = 0; q < PX; ++q)
+          xf[f][q] = *reinterpret_cast<const u4v*>(stx + cx * CBX +
+                                                   lds_slot<CBX, PXN>(cx, gq * PX + q) * 16);
+      }
+      if constexpr (CPLX) {
+#pragma unroll
+        for (int fj = 0; fj < 2; ++fj) {
+          const u4v nxi = neg_u4(xf[fj][1]);
+#pragma unroll
+          for (int fi = 0; fi < 2; ++fi) {
+            f16v re = acc_re[fi][fj], im = acc_im[fi][fj];
+            re = mfma(xf[fj][0], tf[fi][1], re);
+            im = mfma(xf[fj][1], tf[fi][1], im);
+            re = mfma(nxi, tf[fi][3], re);
+            im = mfma(xf[fj][0], tf[fi][3], im);
+            re = mfma(xf[fj][0], tf[fi][0], re);
+            im = mfma(xf[fj][1], tf[fi][0], im);
+            re = mfma(nxi, tf[fi][2], re);
+            im = mfma(xf[fj][0], tf[fi][2], im);
+            acc_re[fi][fj] = re;
+            acc_im[fi][fj] = im;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int fj = 0; fj < 2; ++fj)
+#pragma unroll
+          for (int fi = 0; fi < 2; ++fi) {
+            f16v re = acc_re[fi][fj];
+            re = mfma(xf[fj][0], tf[fi][1], re);
+            re = mfma(xf[fj][0], tf[fi][0], re);
+            acc_re[fi][fj] = re;
+          }
+      }
+    }
+  }
+  if constexpr (SPLIT)
+    store_partial<CPLX>(tp.ws + (int64_t)u * (CPLX ? 2 : 1) * (TBM * TBN), acc_re, acc_im, wi, wj,
+                        l32, h);
+  else
+    epilogue<CPLX>(g, acc_re, acc_im, i0, j0, wi, wj, l32, h);
+}
+
 // Split-K tail: sum the slices' partial tiles (FP64) and apply the
 // Chebyshev-step update, one element per thread, rows fastest.
 template <bool CPLX>
@@ -436,27 +596,39 @@ int device_cus() {
   return n;
 }
 
+// 32-deep chunks for the two-term products unless CHASE_BF16_KCHUNK=16 (the
+// 16-deep kernel, kept for the three-term products and for comparison).
+bool two_term_k32() {
+  static const bool on = [] {
+    const char* e = std::getenv("CHASE_BF16_KCHUNK");
+    return !(e && std::atoi(e) == 16);
+  }();
+  return on;
+}
+
 void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st, int terms) {
   if (g.M <= 0 || g.N <= 0) return;
-  CHASE_REQUIRE(g.a_s8 && g.b_s8 && g.s8_groups > 0 && g.s8_groups % (S8_KPAD / 8) == 0,
+  CHASE_REQUIRE(g.a_s8 && g.b_s8 && g.s8_groups > 0 && g.s8_groups % (KC / 8) == 0,
                 "split-BF16 operands missing");
   CHASE_REQUIRE(g.s8_groups * 8 >= g.K, "split-BF16 operands shorter than K");
+  CHASE_REQUIRE(terms == 2 || terms == 3, "split-BF16 products take two or three terms");
+  const bool k32 = terms == 2 && g.s8_groups % (KC2 / 8) == 0 && two_term_k32();
   const int tiles_m = (int)((g.M + TBM - 1) / TBM);
   const int tiles_n = (int)((g.N + TBN - 1) / TBN);
   const int ntiles = tiles_m * tiles_n;
-  const int64_t nchunks = g.s8_groups / (KC / 8);
+  const int64_t nchunks = g.s8_groups / ((k32 ? KC2 : KC) / 8);
   // One workgroup per CU (LDS-bound), so a launch runs in rounds of `cus`
   // tiles.  A last round filled at most half is run as a split-K tail: its
-  // tiles in K slices of at least kMinChunks chunks on the idle CUs, the FP32
+  // tiles in K slices of at least 256 rows of K on the idle CUs, the FP32
   // partial tiles summed by a second kernel.
-  constexpr int64_t kMinChunks = 16;
+  const int64_t min_chunks = 256 / (k32 ? KC2 : KC);
   const int cus = device_cus();
   TailPlan tp{0, 0, 1, nchunks, g.s8_tail};
   if (g.s8_tail && cus > 0) {
     const int rem = ntiles % cus;
     if (rem > 0 && 2 * rem <= cus) {
       const int64_t want = std::min<int64_t>(
-          {(int64_t)(cus / rem), (int64_t)(S8_TAIL_SLOTS / rem), nchunks / kMinChunks});
+          {(int64_t)(cus / rem), (int64_t)(S8_TAIL_SLOTS / rem), nchunks / min_chunks});
       if (want >= 2) {
         tp.cps = (nchunks + want - 1) / want;
         tp.slices = (int)((nchunks + tp.cps - 1) / tp.cps);
@@ -465,11 +637,16 @@ void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st, int terms) {
       }
     }
   }
-  CHASE_REQUIRE(terms == 2 || terms == 3, "split-BF16 products take two or three terms");
   const int whole = ntiles - tp.rem;
   if (whole > 0) {
     const int grid_x = (whole + 7) / 8 * 8;
-    if (cplx && terms == 3)
+    if (cplx && k32)
+      hipLaunchKernelGGL((gemm_bf16x2_k32_kernel<true, false>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, whole, tp);
+    else if (k32)
+      hipLaunchKernelGGL((gemm_bf16x2_k32_kernel<false, false>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, whole, tp);
+    else if (cplx && terms == 3)
       hipLaunchKernelGGL((gemm_bf16x3_kernel<true, false, 3>), dim3(grid_x), dim3(NTHR), 0, st, g,
                          tiles_n, whole, tp);
     else if (cplx)
@@ -488,23 +665,29 @@ void gemm_bf16x3(bool cplx, const GemmArgs& g, hipStream_t st, int terms) {
     const int grid_x = (items + 7) / 8 * 8;
     const int64_t elems = (int64_t)tp.rem * TBM * TBN;
     const unsigned fin = (unsigned)std::min<int64_t>((elems + 255) / 256, 8192);
-    if (cplx) {
-      if (terms == 3)
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 3>), dim3(grid_x), dim3(NTHR), 0, st,
-                           g, tiles_n, ntiles, tp);
-      else
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 2>), dim3(grid_x), dim3(NTHR), 0, st,
-                           g, tiles_n, ntiles, tp);
+    if (cplx && k32)
+      hipLaunchKernelGGL((gemm_bf16x2_k32_kernel<true, true>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, ntiles, tp);
+    else if (k32)
+      hipLaunchKernelGGL((gemm_bf16x2_k32_kernel<false, true>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, ntiles, tp);
+    else if (cplx && terms == 3)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 3>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, ntiles, tp);
+    else if (cplx)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<true, true, 2>), dim3(grid_x), dim3(NTHR), 0, st, g,
+                         tiles_n, ntiles, tp);
+    else if (terms == 3)
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 3>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, ntiles, tp);
+    else
+      hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 2>), dim3(grid_x), dim3(NTHR), 0, st,
+                         g, tiles_n, ntiles, tp);
+    CHASE_HIP(hipGetLastError());
+    if (cplx)
       hipLaunchKernelGGL(tail_finish_k<true>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
-    } else {
-      if (terms == 3)
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 3>), dim3(grid_x), dim3(NTHR), 0, st,
-                           g, tiles_n, ntiles, tp);
-      else
-        hipLaunchKernelGGL((gemm_bf16x3_kernel<false, true, 2>), dim3(grid_x), dim3(NTHR), 0, st,
-                           g, tiles_n, ntiles, tp);
+    else
       hipLaunchKernelGGL(tail_finish_k<false>, dim3(fin), dim3(256), 0, st, g, tiles_n, tp);
-    }
     CHASE_HIP(hipGetLastError());
   }
 }

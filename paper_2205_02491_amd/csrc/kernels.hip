@@ -256,6 +256,86 @@ __global__ void check_finite_k(const double* __restrict__ X, int64_t ldx, int64_
   }
 }
 
+// ------------------------------------------------------------------ start blocks
+// Counter-based normal draws for start blocks the caller does not supply:
+// scalar c of the stream (column-major, re/im interleaved) takes two
+// uniforms from SplitMix64 (Steele, Lea and Flood, 2014: a Weyl sequence
+// through a 64-bit finaliser) at counters 2c and 2c+1 of its key, and the
+// Box-Muller transform turns them into one N(0, 1) value.
+__device__ inline uint64_t splitmix64(uint64_t z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void fill_gaussian_k(double* __restrict__ X, int64_t ld_scalars, int64_t rows_scalars,
+                                int64_t k, uint64_t key) {
+  const int64_t total = rows_scalars * k;
+  for (int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; c < total;
+       c += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t j = c / rows_scalars, i = c - j * rows_scalars;
+    const uint64_t a = splitmix64(key + 2 * (uint64_t)c), b = splitmix64(key + 2 * (uint64_t)c + 1);
+    const double u1 = (double)((a >> 11) + 1) * 0x1.0p-53;  // (0, 1]
+    const double u2 = (double)(b >> 11) * 0x1.0p-53;        // [0, 1)
+    X[i + j * ld_scalars] = sqrt(-2.0 * log(u1)) * cospi(2.0 * u2);
+  }
+}
+
+// ------------------------------------------------------------------ debug checks
+// Largest |A_ij - conj(A_ji)| (mode 0, square A) or |A_ij - delta_ij| (mode
+// 1) into out[0] and largest |A_ij| into out[1], over 32 x 32 tiles staged
+// through LDS so that both reads are coalesced.  out[] must start at zero;
+// maxima of non-negative doubles are taken on their bit patterns.
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void max_defect_k(const double* __restrict__ A, int64_t lda,
+                                                     int64_t n, int mode,
+                                                     unsigned long long* out) {
+  constexpr int W = CPLX ? 2 : 1;
+  __shared__ double tile[32][33][W];
+  __shared__ double red[2][TPB];
+  const int64_t ti = (int64_t)blockIdx.x * 32, tj = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  double dmax = 0.0, amax = 0.0;
+  if (mode == 0) {
+    // tile (tj, ti) into LDS, read back transposed
+    for (int r = ty; r < 32; r += 8) {
+      const int64_t i = tj + tx, j = ti + r;
+      for (int w = 0; w < W; ++w)
+        tile[r][tx][w] = (i < n && j < n) ? A[(i + j * lda) * W + w] : 0.0;
+    }
+    __syncthreads();
+  }
+  for (int r = ty; r < 32; r += 8) {
+    const int64_t i = ti + tx, j = tj + r;
+    if (i >= n || j >= n) continue;
+    double re = A[(i + j * lda) * W], im = CPLX ? A[(i + j * lda) * W + 1] : 0.0;
+    amax = fmax(amax, CPLX ? hypot(re, im) : fabs(re));
+    if (mode == 0) {
+      // A(j, i) = tile[tx][r]
+      re -= tile[tx][r][0];
+      if (CPLX) im += tile[tx][r][W - 1];
+    } else if (i == j) {
+      re -= 1.0;
+    }
+    dmax = fmax(dmax, CPLX ? hypot(re, im) : fabs(re));
+  }
+  red[0][threadIdx.x] = dmax;
+  red[1][threadIdx.x] = amax;
+  __syncthreads();
+  for (int s = TPB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      red[0][threadIdx.x] = fmax(red[0][threadIdx.x], red[0][threadIdx.x + s]);
+      red[1][threadIdx.x] = fmax(red[1][threadIdx.x], red[1][threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicMax(&out[0], (unsigned long long)__double_as_longlong(red[0][0]));
+    atomicMax(&out[1], (unsigned long long)__double_as_longlong(red[1][0]));
+  }
+}
+
 // ------------------------------------------------------------------ Lanczos
 // Block matrix-vector product W = H Q for nv <= 8 vectors, H read once from
 // HBM (column-major, coalesced along rows).  The columns of H are split over
@@ -774,6 +854,34 @@ void to_f32(bool cplx, const void* src, int64_t lds, void* dst, int64_t n, hipSt
   CHASE_HIP(hipGetLastError());
 }
 
+void fill_gaussian(bool cplx, void* X, int64_t ldx, int64_t n, int64_t k, uint64_t seed,
+                   uint64_t stream_id, hipStream_t st) {
+  if (n <= 0 || k <= 0) return;
+  const int W = cplx ? 2 : 1;
+  // one key per (seed, stream): the counters of different streams never meet
+  const uint64_t key = (seed * 0x100000001B3ull + stream_id) << 40;
+  hipLaunchKernelGGL(fill_gaussian_k, dim3(blocks_for(n * W * k, TPB * 4, 65536)), dim3(TPB), 0,
+                     st, static_cast<double*>(X), ldx * W, n * W, k, key);
+  CHASE_HIP(hipGetLastError());
+}
+
+void max_defect(bool cplx, const void* A, int64_t lda, int64_t n, int mode, double* out2,
+                hipStream_t st) {
+  fill_zero(out2, 2 * sizeof(double), st);
+  if (n <= 0) return;
+  const unsigned t = (unsigned)((n + 31) / 32);
+  CHASE_REQUIRE(t <= 65535, "matrix too large for the debug check");
+  if (cplx)
+    hipLaunchKernelGGL(max_defect_k<true>, dim3(t, t), dim3(TPB), 0, st,
+                       static_cast<const double*>(A), lda, n, mode,
+                       reinterpret_cast<unsigned long long*>(out2));
+  else
+    hipLaunchKernelGGL(max_defect_k<false>, dim3(t, t), dim3(TPB), 0, st,
+                       static_cast<const double*>(A), lda, n, mode,
+                       reinterpret_cast<unsigned long long*>(out2));
+  CHASE_HIP(hipGetLastError());
+}
+
 void check_finite(bool cplx, const void* X, int64_t ldx, int64_t n, int64_t k, int* flags,
                   hipStream_t st) {
   if (n <= 0 || k <= 0) return;
@@ -865,7 +973,8 @@ void lanczos_run(bool cplx, const void* Hv, int64_t ldh, int64_t n, const void* 
   const int vb = (int)std::min<int64_t>(LZ_VEC_BLOCKS, (n + TPB - 1) / TPB);
 
   // q_1 = s / ||s|| ; q_0 = 0
-  CHASE_HIP(hipMemcpyAsync(w, Sv, (size_t)n * nv * W * 8, hipMemcpyDeviceToDevice, st));
+  if (Sv != w)
+    CHASE_HIP(hipMemcpyAsync(w, Sv, (size_t)n * nv * W * 8, hipMemcpyDeviceToDevice, st));
   fill_zero(qprev, (int64_t)n * nv * W * 8, st);
   auto orth = [&](int with_alpha, double* alpha_out) {
     if (cplx)

@@ -12,6 +12,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <numeric>
@@ -62,6 +63,7 @@ struct chase_handle_s {
   bool tape_valid = false;
   rocblas_handle rb = nullptr;
   std::vector<hipEvent_t> evs;
+  hipEvent_t eig_ev[2] = {nullptr, nullptr};  // around the small eigensolve
   std::vector<void*> allocs;
 };
 
@@ -573,7 +575,7 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
 // (h->d_evals, h->d_res).  Scratch: P (n x k, ld n), Zb (n x k, ld n).
 void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq, int k,
              double norm_scale, void* P, void* Zb, double* t_rr, double* t_resid,
-             hipStream_t st, void* Rout = nullptr, int64_t ldr = 0) {
+             hipStream_t st, void* Rout = nullptr, int64_t ldr = 0, double* t_eig = nullptr) {
   const int64_t n = h->n;
   const bool cplx = h->cplx;
   auto t0 = clk::now();
@@ -581,6 +583,7 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
   gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
   // G = Q^H P, exactly Hermitian
   gram(h, Q, ldq, P, n, n, k, k, h->G, k, true, st);
+  if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[0], st));
   if (cplx)
     rb_check(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
                               static_cast<rocblas_double_complex*>(h->G), k, h->d_evals, h->d_E,
@@ -590,6 +593,7 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
     rb_check(rocsolver_dsyevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
                               static_cast<double*>(h->G), k, h->d_evals, h->d_E, h->d_info),
              "dsyevd");
+  if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[1], st));
   // Ritz vectors Z = Q W
   gemm_nn(h, n, k, k, Q, ldq, h->G, k, Zb, n, st);
   CHASE_HIP(hipStreamSynchronize(st));
@@ -609,6 +613,11 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
   auto t2 = clk::now();
   if (t_rr) *t_rr += secs(t0, t1);
   if (t_resid) *t_resid += secs(t1, t2);
+  if (t_eig) {
+    float ms = 0.f;
+    CHASE_HIP(hipEventElapsedTime(&ms, h->eig_ev[0], h->eig_ev[1]));
+    *t_eig += ms * 1e-3;
+  }
 }
 
 void check_info(chase_handle_s* h, hipStream_t st, const char* what) {
@@ -620,6 +629,42 @@ void check_info(chase_handle_s* h, hipStream_t st, const char* what) {
                                        std::to_string(info) + ")");
 }
 
+// The Lanczos step on the given buffers: runs, tridiagonals to the host,
+// bounds (Zhou-Li b_sup, lowest Ritz value, density-of-states estimate of
+// the n_e-th eigenvalue).
+Bounds lanczos_on(bool cplx, LanczosBufs& lz, const void* H, int64_t ldh, int64_t n, int ne,
+                  const void* S, int nv, int steps, std::vector<double>* a_out,
+                  std::vector<double>* b_out, std::vector<int>* lens, hipStream_t st) {
+  lanczos_run(cplx, H, ldh, n, S, nv, steps, lz, st);
+  std::vector<double> a((size_t)steps * nv), b((size_t)steps * nv);
+  CHASE_HIP(hipMemcpyAsync(a.data(), lz.alpha, a.size() * 8, hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipMemcpyAsync(b.data(), lz.beta, b.size() * 8, hipMemcpyDeviceToHost, st));
+  CHASE_HIP(hipStreamSynchronize(st));
+  for (double x : a)
+    if (!std::isfinite(x)) throw Error(CHASE_ERR_NUMERIC, "non-finite Lanczos coefficients");
+  Bounds bd = lanczos_bounds(a, b, nv, steps, n, ne, lens);
+  if (a_out) *a_out = a;
+  if (b_out) *b_out = b;
+  return bd;
+}
+
+// Lanczos run-major output arrays from the step-major device layout.
+void lanczos_outputs(const Bounds& bd, const std::vector<double>& a, const std::vector<double>& b,
+                     const std::vector<int>& lens, int nvec, int steps, double* b_sup,
+                     double* mu_1, double* mu_ne, double* alpha_host, double* beta_host,
+                     int* steps_host) {
+  if (b_sup) *b_sup = bd.b_sup;
+  if (mu_1) *mu_1 = bd.mu_1;
+  if (mu_ne) *mu_ne = bd.mu_ne;
+  for (int r = 0; r < nvec; ++r)
+    for (int j = 0; j < steps; ++j) {
+      if (alpha_host) alpha_host[(size_t)r * steps + j] = a[(size_t)j * nvec + r];
+      if (beta_host) beta_host[(size_t)r * steps + j] = b[(size_t)j * nvec + r];
+    }
+  if (steps_host)
+    for (int r = 0; r < nvec; ++r) steps_host[r] = lens[r];
+}
+
 Bounds do_lanczos(chase_handle_s* h, const void* H, int64_t ldh, const void* S, int nv, int steps,
                   std::vector<double>* a_out, std::vector<double>* b_out, std::vector<int>* lens,
                   hipStream_t st, double* gemv_s = nullptr) {
@@ -629,12 +674,14 @@ Bounds do_lanczos(chase_handle_s* h, const void* H, int64_t ldh, const void* S, 
     h->evs.push_back(e);
   }
   h->lz.gemv_ev = gemv_s ? h->evs.data() : nullptr;
-  lanczos_run(h->cplx, H, ldh, h->n, S, nv, steps, h->lz, st);
+  Bounds bd;
+  try {
+    bd = lanczos_on(h->cplx, h->lz, H, ldh, h->n, h->ne, S, nv, steps, a_out, b_out, lens, st);
+  } catch (...) {
+    h->lz.gemv_ev = nullptr;
+    throw;
+  }
   h->lz.gemv_ev = nullptr;
-  std::vector<double> a((size_t)steps * nv), b((size_t)steps * nv);
-  CHASE_HIP(hipMemcpyAsync(a.data(), h->lz.alpha, a.size() * 8, hipMemcpyDeviceToHost, st));
-  CHASE_HIP(hipMemcpyAsync(b.data(), h->lz.beta, b.size() * 8, hipMemcpyDeviceToHost, st));
-  CHASE_HIP(hipStreamSynchronize(st));
   if (gemv_s) {
     *gemv_s = 0.0;
     for (int j = 0; j < steps; ++j) {
@@ -643,11 +690,6 @@ Bounds do_lanczos(chase_handle_s* h, const void* H, int64_t ldh, const void* S, 
       *gemv_s += ms * 1e-3;
     }
   }
-  for (double x : a)
-    if (!std::isfinite(x)) throw Error(CHASE_ERR_NUMERIC, "non-finite Lanczos coefficients");
-  Bounds bd = lanczos_bounds(a, b, nv, steps, h->n, h->ne, lens);
-  if (a_out) *a_out = a;
-  if (b_out) *b_out = b;
   return bd;
 }
 
@@ -682,6 +724,27 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   chase_stats stats{};
   auto T0 = clk::now();
   const int deg0 = degree + (degree & 1);
+
+  if (o.debug) {
+    // H Hermitian is a precondition of the method (and of the split-BF16
+    // copy, which stores conj(H) as the transpose)
+    double d[2];
+    max_defect(cplx, H, ldh, n, 0, h->d_res, st);
+    CHASE_HIP(hipMemcpyAsync(d, h->d_res, sizeof(d), hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    stats.debug_herm_defect = d[1] > 0 ? d[0] / d[1] : 0.0;
+    if (!std::isfinite(d[0]) || !std::isfinite(d[1]))
+      throw Error(CHASE_ERR_NUMERIC, "H holds non-finite values");
+    if (d[0] > 1e-12 * d[1])
+      throw Error(CHASE_ERR_ARG, "H is not Hermitian: max |H - H^H| = " + std::to_string(d[0]) +
+                                     " (max |H| = " + std::to_string(d[1]) + ")");
+  }
+  // start blocks the caller did not supply: seeded draws into the Lanczos
+  // buffer (S) and the search block (V0)
+  if (!S) {
+    fill_gaussian(cplx, h->lz.w, n, n, o.lanczos_vecs, (uint64_t)(uint32_t)o.seed, 1, st);
+    S = h->lz.w;
+  }
 
   // Lanczos spectral bounds
   const int steps = (int)std::min<int64_t>(o.lanczos_steps, n);
@@ -730,7 +793,10 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   if (plow == PREC_F32 && mixed && h->H32) to_f32(cplx, H, ldh, h->H32, n, st);
   if (is_split_bf16(plow)) split_h(h, H, ldh, st);
 
-  CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
+  if (V0)
+    CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
+  else
+    fill_gaussian(cplx, h->V, n, n, ne, (uint64_t)(uint32_t)o.seed, 0, st);
   std::vector<int> m(ne, deg0);
   std::vector<double> lam(ne, 0.0), res(ne, INFINITY);
   // Precision policy (mixed mode).  low[j]: column j is filtered with FP32
@@ -830,11 +896,34 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   // lock before any filtering, the first filter uses the degrees optimised
   // from the start block's residuals, and the mixed modes filter its Ritz
   // vectors in the defect-correction form from the first pass on.
+  // Debug mode: every phase's output must be finite, and the block must be
+  // orthonormal after each QR step (max |V^H V - I| over the whole block).
+  auto debug_check = [&](const char* phase, int col0, bool orth) {
+    if (!o.debug) return;
+    int bad = 0;
+    fill_zero(h->d_flags, sizeof(int), st);
+    check_finite(cplx, off(h->V, (int64_t)col0 * n, h->esz), n, n, ne - col0, h->d_flags, st);
+    CHASE_HIP(hipMemcpyAsync(&bad, h->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    if (bad) throw Error(CHASE_ERR_NUMERIC, std::string("non-finite values after ") + phase);
+    if (!orth) return;
+    double d[2];
+    gram(h, h->V, n, h->V, n, n, ne, ne, h->R, ne, true, st);
+    max_defect(cplx, h->R, ne, ne, 1, h->d_res, st);
+    CHASE_HIP(hipMemcpyAsync(d, h->d_res, sizeof(d), hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    stats.debug_orth_defect = std::max(stats.debug_orth_defect, d[0]);
+    if (!(d[0] <= 1e-8))
+      throw Error(CHASE_ERR_NUMERIC, std::string("block not orthonormal after ") + phase +
+                                         ": max |Q^H Q - I| = " + std::to_string(d[0]));
+  };
   bool have_ritz = false;
   if (o.initial_rr) {
     qr_step(h, h->V, n, ne, 0, h->W, &stats, st);
+    debug_check("QR", 0, true);
     rr_step(h, H, ldh, h->V, n, ne, norm_est, h->W, h->Z, &stats.t_rr, &stats.t_resid, st,
-            mixed ? h->Rres : nullptr, n);
+            mixed ? h->Rres : nullptr, n, &stats.t_rr_eig);
+    debug_check("Rayleigh-Ritz", 0, false);
     have_ritz = true;
     if (after_rr(-1, ne, 0)) stats.iterations = 0;
   }
@@ -861,13 +950,18 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     }
     auto F1 = clk::now();
     stats.t_filter += secs(F0, F1);
+    debug_check("the filter", L, false);
     // ---- QR of [Y V]
+    F1 = clk::now();
     qr_step(h, h->V, n, ne, L, h->W, &stats, st);
     auto Q1 = clk::now();
     stats.t_qr += secs(F1, Q1);
+    debug_check("QR", 0, true);
     // ---- Rayleigh-Ritz + residuals on the active part
     rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
-            &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n);
+            &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n,
+            &stats.t_rr_eig);
+    debug_check("Rayleigh-Ritz", L, false);
     if (after_rr(it, ka, n64)) break;
   }
   // ---- output: lowest nev of the locked pairs (or of all pairs on NOCONV)
@@ -1084,6 +1178,10 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
     rb_check(rocblas_create_handle(&h->rb), "rocblas_create_handle");
+    CHASE_HIP(hipEventCreate(&h->eig_ev[0]));
+    CHASE_HIP(hipEventCreate(&h->eig_ev[1]));
+    if (const char* e = std::getenv("CHASE_DEBUG"))
+      if (std::atoi(e) != 0) h->opts.debug = 1;
     *out = h;
   });
   if (st != CHASE_OK && h) chase_destroy(h);
@@ -1097,6 +1195,8 @@ void chase_destroy(chase_handle_t h) {
   for (void* p : h->allocs) (void)hipFree(p);
   if (h->tape) (void)hipFree(h->tape);
   for (hipEvent_t e : h->evs) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->eig_ev)
+    if (e) (void)hipEventDestroy(e);
   if (h->rb) rocblas_destroy_handle(h->rb);
   delete h;
 }
@@ -1107,7 +1207,7 @@ chase_status chase_solve(chase_handle_t h, const void* H, int64_t ldh, double to
   bool noconv = false;
   chase_status s = guarded([&] {
     CHASE_REQUIRE(h != nullptr, "handle is NULL");
-    CHASE_REQUIRE(H && V0 && S && evals_host && evecs_dev, "NULL pointer argument");
+    CHASE_REQUIRE(H && evals_host && evecs_dev, "NULL pointer argument");
     CHASE_REQUIRE(ldh >= h->n && ldv >= h->n, "leading dimension smaller than n");
     CHASE_REQUIRE(tol > 0 && std::isfinite(tol), "tol must be positive");
     CHASE_REQUIRE(degree >= 2 && degree <= std::min(h->opts.max_deg + 1, kMaxDegree),
@@ -1139,16 +1239,8 @@ chase_status chase_lanczos(chase_handle_t h, const void* H, int64_t ldh, const v
     std::vector<double> a, b;
     std::vector<int> lens;
     Bounds bd = do_lanczos(h, H, ldh, S, nvec, steps, &a, &b, &lens, st);
-    if (b_sup) *b_sup = bd.b_sup;
-    if (mu_1) *mu_1 = bd.mu_1;
-    if (mu_ne) *mu_ne = bd.mu_ne;
-    for (int r = 0; r < nvec; ++r)
-      for (int j = 0; j < steps; ++j) {
-        if (alpha_host) alpha_host[(size_t)r * steps + j] = a[(size_t)j * nvec + r];
-        if (beta_host) beta_host[(size_t)r * steps + j] = b[(size_t)j * nvec + r];
-      }
-    if (steps_host)
-      for (int r = 0; r < nvec; ++r) steps_host[r] = lens[r];
+    lanczos_outputs(bd, a, b, lens, nvec, steps, b_sup, mu_1, mu_ne, alpha_host, beta_host,
+                    steps_host);
   });
 }
 

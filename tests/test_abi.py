@@ -40,6 +40,29 @@ def test_default_opts():
     o = pk.default_opts()
     assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
             o.max_iter, o.filter_prec, o.initial_rr, o.fp64_tail) == (36, 2, 1, 25, 4, 50, 0, 0, -1)
+    assert (o.seed, o.debug) == (0, 0)
+
+
+@pytest.mark.parametrize("struct", ["chase_opts", "chase_stats"])
+def test_binding_structs_match_the_header(tmp_path, struct):
+    """Every field of the ctypes mirrors sits at the offset the C compiler
+    gives it in include/chase.h, and the sizes agree (a field added to one
+    side only would shift the library's reads and writes)."""
+    import subprocess
+    pk = _lib()
+    cls = {"chase_opts": pk.Opts, "chase_stats": pk.Stats}[struct]
+    lines = [f'printf("%zu\\n", offsetof({struct}, {f}));' for f, _ in cls._fields_]
+    lines.append(f'printf("%zu\\n", sizeof({struct}));')
+    src = tmp_path / "layout.c"
+    src.write_text('#include <stddef.h>\n#include <stdio.h>\n#include "chase.h"\n'
+                   "int main(void) {\n" + "\n".join(lines) + "\nreturn 0; }\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True, capture_output=True)
+    out = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True,
+                                          check=True).stdout.split()]
+    assert out[:-1] == [getattr(cls, f).offset for f, _ in cls._fields_]
+    assert out[-1] == ctypes.sizeof(cls)
 
 
 def test_workspace_bytes_matches_one_gpu_memory_estimate():
@@ -59,14 +82,14 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
         assert b_real < b
     o = pk.default_opts(filter_prec=1)
     assert pk.chase_workspace_bytes(20000, 1000, 300, opts=o) >= 20000 ** 2 * 8
-    # split-BF16 mode adds the split of H (rows padded to 16, columns to 256,
+    # split-BF16 mode adds the split of H (rows padded to 32, columns to 256,
     # 4 bf16 per complex entry), two splits of the block (columns padded to
     # 128: a step's operand and the next step's, written by its epilogue),
     # 256 FP32 partial tiles of 256 x 128 (re and im) for the GEMM's split-K
     # tail and the residual block
     for n, nev, nex, cplx in [(30000, 1500, 500, True), (1000, 100, 40, False)]:
         ne, esz = nev + nex, (16 if cplx else 8)
-        rows = -(-n // 16) * 16
+        rows = -(-n // 32) * 32
         per = 8 if cplx else 4
         extra = rows * per * (-(-n // 256) * 256) + 2 * rows * per * (-(-ne // 128) * 128) \
             + 256 * 256 * 128 * (2 if cplx else 1) * 4 + n * ne * esz
@@ -265,3 +288,4 @@ def test_binding_rejects_mismatched_handles_and_shapes():
     for fn, msg in cases:
         with pytest.raises(ValueError, match=msg):
             fn()
+

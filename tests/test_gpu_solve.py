@@ -275,3 +275,52 @@ def test_solve_table1_suite_matches_oracle_counts(pk, kind):
         assert abs(st["matvecs_fp64"] - st_o.matvecs) <= 0.02 * st_o.matvecs, \
             (st["matvecs_fp64"], st_o.matvecs)
     assert np.all(res <= p.tol)
+
+
+def test_solve_library_drawn_start_blocks(pk):
+    """V0 and S omitted (NULL through the C ABI): the library draws both from
+    its counter-based generator, seeded by opts.seed.  The same seed gives
+    bit-identical solves, another seed another start block; every solve
+    meets the accuracy bar against the planted spectrum."""
+    announce("solve with library-drawn start blocks")
+    p = gen.make_uniform(n=600, nev=30, nex=15, cfg=31)
+    H = to_gpu(p.H)
+    norm = max(abs(p.lam[0]), abs(p.lam[-1]))
+    runs = []
+    for seed in (0, 0, 7):
+        ev, vec, res, st = pk.chase_solve(H, p.nev, p.nex, p.tol, p.deg,
+                                          opts=pk.default_opts(seed=seed))
+        assert st["converged"]
+        assert np.max(np.abs(ev - p.lam[:p.nev])) <= 2 * p.tol * norm
+        assert np.all(res <= p.tol)
+        v = to_np(vec)
+        assert np.linalg.norm(v.conj().T @ v - np.eye(p.nev)) < 1e-12
+        runs.append((ev, v, st))
+    assert np.array_equal(runs[0][0], runs[1][0]) and np.array_equal(runs[0][1], runs[1][1])
+    assert runs[0][2]["matvecs_fp64"] == runs[1][2]["matvecs_fp64"]
+    assert not np.array_equal(runs[0][1], runs[2][1])
+
+
+def test_debug_mode_checks(pk, monkeypatch):
+    """Debug mode: the solve reports max |H - H^H| / max |H| and the largest
+    max |Q^H Q - I| after its QR steps, and gives the same result as without
+    the checks; a matrix that is not Hermitian is refused with ERR_ARG
+    before any work.  CHASE_DEBUG=1 at handle creation turns the mode on."""
+    announce("debug mode")
+    p = gen.make_uniform(n=500, nev=20, nex=10, cfg=32)
+    H = to_gpu(p.H)
+    V0, S = to_gpu(p.V0), to_gpu(p.S)
+    ev0, v0, _, st0 = pk.chase_solve(H, p.nev, p.nex, p.tol, p.deg, V0, S)
+    ev, v, _, st = pk.chase_solve(H, p.nev, p.nex, p.tol, p.deg, V0, S,
+                                  opts=pk.default_opts(debug=1))
+    assert np.array_equal(ev, ev0) and np.array_equal(to_np(v), to_np(v0))
+    assert st0["debug_orth_defect"] == 0.0 and st0["debug_herm_defect"] == 0.0
+    assert st["debug_herm_defect"] == 0.0          # (H + H^H)/2 is exactly Hermitian
+    assert 0.0 < st["debug_orth_defect"] < 1e-13
+    Hb = H.clone()
+    Hb[0, 1] += 1e-6
+    with pytest.raises(pk.ChaseError, match="not Hermitian"):
+        pk.chase_solve(Hb, p.nev, p.nex, p.tol, p.deg, V0, S, opts=pk.default_opts(debug=1))
+    monkeypatch.setenv("CHASE_DEBUG", "1")
+    with pytest.raises(pk.ChaseError, match="not Hermitian"):
+        pk.chase_solve(Hb, p.nev, p.nex, p.tol, p.deg, V0, S)

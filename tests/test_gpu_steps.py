@@ -242,6 +242,84 @@ def test_filter_bf16x3_whole_tiles_and_split_tail(pk, cplx, prec):
     assert np.median(err) > ERR[prec][1], np.median(err)
 
 
+def _bf16(x):
+    """Round to bf16 as the kernels do: to float32 first, then to nearest
+    even on the upper 16 bits (finite values)."""
+    u = np.asarray(x, dtype=np.float64).astype(np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _split(x):
+    """hi = bf16(x), lo = bf16(x - hi), componentwise for complex x."""
+    if np.iscomplexobj(x):
+        (hr, lr), (hi_, li) = _split(x.real), _split(x.imag)
+        return hr + 1j * hi_, lr + 1j * li
+    hi = _bf16(x)
+    return hi, _bf16(x - hi)
+
+
+def _dyadic(g, shape, cplx):
+    """Entries i + f 2^-9 with i in {-2,-1,1,2} and f in {-1,0,1}: the split
+    is exact (hi = i, lo = f 2^-9), and sums of products of such numbers stay
+    multiples of 2^-9 (2^-18 for lo*lo, which no kernel forms)."""
+    def part():
+        return g.choice([-2.0, -1.0, 1.0, 2.0], size=shape) + g.integers(-1, 2, size=shape) * 2.0 ** -9
+    return part() + 1j * part() if cplx else part()
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16x2"])
+@pytest.mark.parametrize("cplx", [True, False])
+@pytest.mark.parametrize("n,k", [(810, 64), (4100, 2100)])
+def test_filter_split_bf16_matches_rounding_emulation(pk, cplx, n, k, prec):
+    """The split-BF16 kernels against an FP64 emulation of their own operand
+    rounding, on inputs that make the first step's sums exact in FP32
+    arithmetic: H and X_0 with entries i + f 2^-9 (exact splits; every partial
+    sum a multiple of 2^-9 far below 2^15), shift gamma = 0 and alpha_1 =
+    -2^-9 (c = 0, e = 400, mu_1 = -512).  Step 2 multiplies the split of X_1
+    (rounded to 16 bits, or to bf16 with two terms, the same way on both
+    sides) and is the last one (degree 2), so what is left is the FP32
+    accumulation of the products (measured 3.6e-7 at most, n=4100 complex),
+    against 1e-6 (three terms, n=4100) to 7e-4 (two terms) for the operands'
+    own rounding; a dropped or misplaced plane, 8-row group, K chunk or tile
+    costs 1e-4 or more.  n=810 pads K; n=4100, k=2100 runs whole tiles and
+    the split-K tail."""
+    announce(f"filter {prec} vs rounding emulation n={n} k={k} cplx={cplx}")
+    g = np.random.Generator(np.random.PCG64(7700 + n + cplx))
+    a = np.triu(_dyadic(g, (n, n), cplx))
+    h = a + np.triu(a, 1).conj().T
+    if cplx:
+        h[np.diag_indices(n)] = h.diagonal().real
+    del a
+    x = _dyadic(g, (n, k), cplx)
+    deg = np.full(k, 2, dtype=np.int32)
+    b_sup, mu_1, mu_ne = 400.0, -512.0, -400.0
+    (a1, c1, b1), (a2, c2, b2) = oracle.filter_coefficients(2, b_sup, mu_1, mu_ne)
+    assert a1 == -2.0 ** -9 and c1 == 0.0 and c2 == 0.0 and b1 == 0.0
+    code = pk.PREC_BF16X3 if prec == "bf16x3" else pk.PREC_BF16X2
+    y, mv = pk.chase_filter(to_gpu(h), to_gpu(x), deg, b_sup, mu_1, mu_ne, prec=code)
+    assert mv == 2 * k
+    cols = np.unique(np.concatenate([np.arange(0, k, max(1, k // 40)), [k - 1]]))
+    h_hi, h_lo = _split(h)
+    assert np.array_equal(h_hi + h_lo, h)
+
+    def product(xs):
+        x_hi, x_lo = _split(xs)
+        p = h_hi @ x_hi + h_lo @ x_hi
+        return p + h_hi @ x_lo if prec == "bf16x3" else p
+
+    xc = x[:, cols]
+    x1 = a1 * product(xc)
+    y_emu = a2 * product(x1) + b2 * xc
+    y_ref, _ = oracle.chebyshev_filter(h, xc, deg[cols], b_sup, mu_1, mu_ne)
+    y = to_np(y)[:, cols]
+    nrm = np.linalg.norm(y_ref, axis=0)
+    e_emu = np.linalg.norm(y - y_emu, axis=0) / nrm
+    e_ref = np.linalg.norm(y - y_ref, axis=0) / nrm
+    announce(f"  max error vs emulation {e_emu.max():.2e}, vs FP64 {e_ref.max():.2e}")
+    assert np.all(e_emu < 2e-6), (e_emu.max(), int(cols[e_emu.argmax()]))
+    assert np.median(e_emu) < 0.5 * np.median(e_ref)
+
 @pytest.mark.parametrize("n,k", [(17, 1), (256, 128), (257, 129), (300, 2)])
 def test_filter_bf16x3_edge_shapes(pk, n, k):
     """Split-BF16 filter at edge shapes: a single column, exact tile
