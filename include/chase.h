@@ -201,6 +201,27 @@ chase_status chase_lanczos(chase_handle_t handle, const void* H_dev, int64_t ldh
                            double* mu_1, double* mu_ne, double* alpha_host,
                            double* beta_host, int* steps_host, void* stream);
 
+/* chase_lanczos without a handle and without allocating device memory, for
+ * callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same computation and outputs as
+ * chase_lanczos for an element type `dtype` and a problem with n_e = nev+nex
+ * wanted columns (n_e sets the density-of-states estimate mu_ne); H_dev
+ * (n x n, ld ldh) and S_dev (n x nvec, ld n) are the caller's, 1 <= nvec
+ * <= 8, 1 <= steps <= min(200, n).  The work buffers (3 n nvec vectors,
+ * the block GEMV's partial sums, the tridiagonals) live in a fixed device
+ * array of 64 MiB that the library holds on every GPU it runs on until the
+ * process ends; a problem that needs more is refused with CHASE_ERR_ARG
+ * before any GPU work (complex, 25 steps: n <= 104000 at nvec = 8, n <= 262000
+ * at nvec = 4; real: about twice that).  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on the same GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Calls no hipMalloc/hipFree and no allocating
+ * library routine; host-side it keeps the small tridiagonals in host memory. */
+chase_status chase_lanczos_noalloc(chase_dtype dtype, const void* H_dev, int64_t ldh,
+                                   int64_t n, int n_e, const void* S_dev, int nvec, int steps,
+                                   double* b_sup, double* mu_1, double* mu_ne,
+                                   double* alpha_host, double* beta_host, int* steps_host,
+                                   void* stream);
+
 /* Chebyshev filter (Eq. (3), scaled so the polynomial is 1 at mu_1, damping
  * [mu_ne, b_sup]).  Column a of X_dev (n x k, ld ldx, in/out) is replaced by
  * p_{m_a}(H) x_a with m_a = degrees_host[a]: even, >= 2, non-decreasing in a.

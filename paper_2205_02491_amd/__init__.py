@@ -27,7 +27,8 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
            4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}
 
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
-            "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
+            "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
+            "chase_filter_ritz", "chase_qr",
             "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_eigvec_adjoint",
             "chase_filter_adjoint", "chase_filter_coefficients", "chase_spectral_bounds",
             "chase_degrees", "chase_last_error"]
@@ -97,6 +98,9 @@ def lib():
     L.chase_solve.restype = ci
     L.chase_lanczos.argtypes = [vp, vp, i64, vp, ci, ci, pd, pd, pd, pd, pd, pi, vp]
     L.chase_lanczos.restype = ci
+    L.chase_lanczos_noalloc.argtypes = [ci, vp, i64, i64, ci, vp, ci, ci, pd, pd, pd, pd, pd, pi,
+                                        vp]
+    L.chase_lanczos_noalloc.restype = ci
     L.chase_filter.argtypes = [vp, vp, i64, vp, i64, ci, pi, cd, cd, cd, ci, ci, pi64, vp]
     L.chase_filter.restype = ci
     L.chase_filter_ritz.argtypes = [vp, vp, i64, vp, i64, vp, i64, pd, ci, pi, cd, cd, cd, ci,
@@ -330,6 +334,37 @@ def chase_lanczos(H, S, steps=None, handle=None, n_e=None, opts=None):
     return out[0].value, out[1].value, out[2].value, a, b, lens
 
 
+def chase_lanczos_noalloc(H, S, n_e, steps=25):
+    """chase_lanczos without a handle and without device allocations: the
+    library's fixed scratch holds the work buffers.  No copy is made of S, so
+    it must already be in the form the library reads: column-major (S.mT
+    contiguous, e.g. a view of an (nvec, n) tensor) and, for complex H, in
+    the library's frame (the column-major buffer of conj(H) is torch's H, so
+    start vectors s of H are passed as s.conj(); chase_lanczos does that
+    conjugating copy itself).  Returns (b_sup, mu_1, mu_ne, alpha[nvec, steps],
+    beta[nvec, steps], lengths), the same as chase_lanczos."""
+    _check_square(H)
+    n = H.shape[0]
+    _check_block(S, n, None, "S")
+    if S.dtype != H.dtype:
+        raise ValueError("S must have H's dtype")
+    if not S.mT.is_contiguous():
+        raise ValueError("S must be column-major (S.mT contiguous): no copy is made here")
+    nvec = S.shape[1]
+    a = np.zeros((nvec, steps))
+    b = np.zeros((nvec, steps))
+    lens = np.zeros(nvec, dtype=np.int32)
+    out = [ctypes.c_double() for _ in range(3)]
+    pd = ctypes.POINTER(ctypes.c_double)
+    _check(lib().chase_lanczos_noalloc(_dtype_code(H), _dev(H), n, n, int(n_e), _dev(S),
+                                       nvec, int(steps), ctypes.byref(out[0]),
+                                       ctypes.byref(out[1]), ctypes.byref(out[2]),
+                                       a.ctypes.data_as(pd), b.ctypes.data_as(pd),
+                                       lens.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                       _stream()))
+    return out[0].value, out[1].value, out[2].value, a, b, lens
+
+
 def chase_filter(H, X, degrees, b_sup, mu_1, mu_ne, prec=PREC_FP64, record_tape=False,
                  handle=None):
     """Chebyshev filter of the columns of X (n x k) with per-column even,
@@ -529,7 +564,8 @@ def chase_degrees(resid, ritz, b_sup, mu_ne, tol, degree=20, opts: Opts | None =
 from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
-           "chase_solve", "chase_lanczos", "chase_filter", "chase_filter_ritz", "chase_qr",
+           "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
+           "chase_filter_ritz", "chase_qr",
            "chase_rayleigh_ritz",
            "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint",
            "chase_filter_coefficients", "chase_spectral_bounds", "chase_degrees", "ChaseEigh",

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -67,9 +68,36 @@ struct chase_handle_s {
   std::vector<void*> allocs;
 };
 
+// Work buffers of chase_lanczos_noalloc: a fixed device array (one copy per
+// GPU, held until the process ends) instead of a handle's workspace.  Host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// each device; the array's name is not a device address on the host.
+constexpr size_t kNoAllocScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_last_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the no-allocation scratch on the current device, looked
+// up once per device.
+char* noalloc_scratch() {
+  int dev = 0;
+  CHASE_HIP(hipGetDevice(&dev));
+  CHASE_REQUIRE(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    CHASE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CHASE_REQUIRE(p != nullptr, "scratch symbol has no device address");
+    g_scratch_ptr[dev] = p;
+  }
+  return static_cast<char*>(g_scratch_ptr[dev]);
+}
 
 using clk = std::chrono::steady_clock;
 double secs(clk::time_point a, clk::time_point b) {
@@ -1239,6 +1267,50 @@ chase_status chase_lanczos(chase_handle_t h, const void* H, int64_t ldh, const v
     std::vector<double> a, b;
     std::vector<int> lens;
     Bounds bd = do_lanczos(h, H, ldh, S, nvec, steps, &a, &b, &lens, st);
+    lanczos_outputs(bd, a, b, lens, nvec, steps, b_sup, mu_1, mu_ne, alpha_host, beta_host,
+                    steps_host);
+  });
+}
+
+chase_status chase_lanczos_noalloc(chase_dtype dtype, const void* H, int64_t ldh, int64_t n,
+                                   int n_e, const void* S, int nvec, int steps, double* b_sup,
+                                   double* mu_1, double* mu_ne, double* alpha_host,
+                                   double* beta_host, int* steps_host, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(dtype == CHASE_C128 || dtype == CHASE_F64, "unknown dtype");
+    CHASE_REQUIRE(n >= 1 && n_e >= 1 && n_e <= n, "sizes out of range (1 <= n_e <= n)");
+    CHASE_REQUIRE(H && S, "NULL pointer argument");
+    CHASE_REQUIRE(ldh >= n, "ldh < n");
+    CHASE_REQUIRE(nvec >= 1 && nvec <= 8, "nvec out of range [1, 8]");
+    CHASE_REQUIRE(steps >= 1 && steps <= 200 && steps <= n, "steps out of range [1, min(200, n)]");
+    const bool cplx = dtype == CHASE_C128;
+    const int W = cplx ? 2 : 1;
+    int splits = 0;
+    const size_t need = lanczos_bytes(cplx, n, nvec, steps, &splits) + 8 * 256;
+    CHASE_REQUIRE(need <= kNoAllocScratchBytes,
+                  "problem needs " + std::to_string(need) +
+                      " bytes of Lanczos buffers, more than the no-allocation scratch (" +
+                      std::to_string(kNoAllocScratchBytes) + " bytes)");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    char* p = noalloc_scratch();
+    auto take = [&p](size_t bytes) {
+      char* q = p;
+      p += (bytes + 255) / 256 * 256;
+      return q;
+    };
+    LanczosBufs lz{};
+    lz.max_splits = splits;
+    lz.q_prev = take((size_t)n * nvec * W * 8);
+    lz.q_cur = take((size_t)n * nvec * W * 8);
+    lz.w = take((size_t)n * nvec * W * 8);
+    lz.wpart = take((size_t)splits * nvec * n * W * 8);
+    lz.dotp = reinterpret_cast<double*>(take(128 * (size_t)nvec * 8));
+    lz.nrmp = reinterpret_cast<double*>(take(128 * (size_t)nvec * 8));
+    lz.alpha = reinterpret_cast<double*>(take((size_t)steps * nvec * 8));
+    lz.beta = reinterpret_cast<double*>(take((size_t)steps * nvec * 8));
+    std::vector<double> a, b;
+    std::vector<int> lens;
+    Bounds bd = lanczos_on(cplx, lz, H, ldh, n, n_e, S, nvec, steps, &a, &b, &lens, st);
     lanczos_outputs(bd, a, b, lens, nvec, steps, b_sup, mu_1, mu_ne, alpha_host, beta_host,
                     steps_host);
   });

@@ -289,3 +289,19 @@ def test_binding_rejects_mismatched_handles_and_shapes():
         with pytest.raises(ValueError, match=msg):
             fn()
 
+
+def test_noalloc_lanczos_refuses_oversized_problems_without_gpu():
+    """The no-allocation Lanczos entry point checks its scratch budget on the
+    host: 200000 complex rows x 8 vectors need more than the 64 MiB array,
+    so the call is refused before any pointer is read or GPU is touched."""
+    pk = _lib()
+    L = pk.lib()
+    out = [ctypes.c_double() for _ in range(3)]
+    st = L.chase_lanczos_noalloc(0, ctypes.c_void_p(256), 200000, 200000, 100,
+                                 ctypes.c_void_p(256), 8, 25, ctypes.byref(out[0]),
+                                 ctypes.byref(out[1]), ctypes.byref(out[2]), None, None, None,
+                                 None)
+    assert st == pk.ERR_ARG and b"scratch" in L.chase_last_error()
+    st = L.chase_lanczos_noalloc(0, ctypes.c_void_p(256), 1000, 1000, 100, None, 4, 25,
+                                 None, None, None, None, None, None, None)
+    assert st == pk.ERR_ARG and b"NULL" in L.chase_last_error()
