@@ -487,6 +487,50 @@ def mode_summary(m, prec, fp64_solve_s):
     return out
 
 
+def library_gemm_reference():
+    """Rates of the vendor's own GEMMs on this GPU (torch -> hipBLASLt /
+    rocBLAS), timed the same way as the library's kernels, as the practical
+    ceiling beside the published peaks: a BF16 GEMM of 30000 x 30000 times
+    30000 x 8000 with N(0, 1) and with zero operands (the chip's clock under
+    MFMA load depends on the data), an FP64 GEMM and a complex128 GEMM of the
+    n=20000 filter step's shape (20000 x 20000 times 20000 x 1300)."""
+    import torch
+
+    def rate(a, b, reps, flops):
+        for _ in range(2):
+            c = a @ b
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            c = a @ b
+        torch.cuda.synchronize()
+        del c
+        return flops / ((time.perf_counter() - t0) / reps) / 1e12
+
+    out = {"source": "torch.matmul (hipBLASLt / rocBLAS)", "unit": "TFLOP/s"}
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    n, k = 30000, 8000
+    a = torch.randn((n, n), device="cuda", dtype=torch.bfloat16, generator=g)
+    b = torch.randn((n, k), device="cuda", dtype=torch.bfloat16, generator=g)
+    out["bf16_random"] = rate(a, b, 10, 2.0 * n * n * k)
+    a.zero_()
+    b.zero_()
+    out["bf16_zeros"] = rate(a, b, 10, 2.0 * n * n * k)
+    del a, b
+    torch.cuda.empty_cache()
+    n, k = 20000, 1300
+    for dt, key, per in ((torch.float64, "fp64", 2.0), (torch.complex128, "complex128", 8.0)):
+        a = torch.randn((n, n), device="cuda", dtype=dt, generator=g)
+        b = torch.randn((n, k), device="cuda", dtype=dt, generator=g)
+        out[key] = rate(a, b, 3, per * n * n * k)
+        del a, b
+        torch.cuda.empty_cache()
+    out["shapes"] = ("bf16: 30000x30000 @ 30000x8000; fp64 and complex128: 20000x20000 @ "
+                     "20000x1300 (complex counted as 8 n^2 k)")
+    return out
+
+
 def mixed_workload_block(pk, precs, steps, warmup):
     """FP64 versus mixed-precision solves on the n=30000 workload (lowest 2000
     eigenvalues those of the (1-2-1) matrix, the rest uniform up to 10;
@@ -531,6 +575,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed-workload", action="store_true",
                     help="skip the n=30000 FP64-versus-mixed block of the default workload")
+    ap.add_argument("--no-library-reference", action="store_true",
+                    help="skip the vendor GEMM rates printed beside the roofline")
+    ap.add_argument("--library-reference", action="store_true",
+                    help="only time the vendor GEMMs (torch -> hipBLASLt / rocBLAS)")
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed solves per mode in the n=30000 block")
     ap.add_argument("--mixed-warmup", type=int, default=0,
@@ -550,6 +598,9 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte "
                          "counters of rocprofv3 --pmc)")
     args = ap.parse_args()
+    if args.library_reference:
+        print(json.dumps(library_gemm_reference()), flush=True)
+        return
     if args.calib_copy:
         import torch
         x = torch.ones(2**27, dtype=torch.float64, device="cuda")  # 1 GiB
@@ -663,6 +714,9 @@ def main():
             f"{out['cpu_baseline']['pieces_s']}, small {out['cpu_baseline']['small_solve']}")
     del H, prob, results
     torch.cuda.empty_cache()
+    if not args.no_library_reference:
+        out["library_gemm_reference"] = library_gemm_reference()
+        log(f"library GEMM reference: {out['library_gemm_reference']}")
     if args.workload == "geometric20k" and not (args.no_mixed_workload or args.gen_elementary):
         # the metric's FP64-versus-mixed comparison on the workload where the
         # mixed-precision policy does its work (many iterations, defect form)

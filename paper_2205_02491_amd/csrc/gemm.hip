@@ -152,22 +152,6 @@ __global__ __launch_bounds__(NTHR) void gemm_kernel(GemmArgs g, int tiles_n, int
   const int t = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (t >= ntiles) return;
   int tm = t / tiles_n, tn = t - tm * tiles_n;
-  if constexpr ((EPI == EPI_CHEB || EPI == EPI_STORE) && TBN == 64) {
-    // Long products (H times a block, K = n): tiles in groups of 4 row
-    // panels x 8 column tiles, so the ~32 workgroups an XCD runs at once
-    // share 4 panels of A and 8 column tiles of B in its L2 (row-major order
-    // would have them share 1-2 panels of A but all of B's columns, which
-    // are then streamed again for every panel).
-    constexpr int GM = 4, GN = 8;
-    const int tiles_m = ntiles / tiles_n;
-    const int r0 = t / (GM * tiles_n) * GM;
-    const int gm = tiles_m - r0 < GM ? tiles_m - r0 : GM;
-    const int rem = t - r0 * tiles_n;
-    const int cg = rem / (gm * GN);
-    const int w = rem - cg * gm * GN;
-    tm = r0 + w % gm;
-    tn = cg * GN + w / gm;
-  }
   if constexpr (EPI == EPI_SPLITK) {
     static_assert(EPI != EPI_SPLITK || TBM == TBN, "square split-K tiles");
     if (g.tri) {
