@@ -146,14 +146,16 @@ def test_filter_adjoint_mixed_degrees_input_gradient(pk):
         assert abs(fd - an) <= 1e-6 * abs(an) + 1e-9 * np.linalg.norm(Gd), (fd, an)
 
 
-def test_filter_adjoint_full_size_daleckii_krein(pk):
-    """Differentiation workload size (n=8000 complex128, nev+nex=260 columns,
-    degree 20): the gradient of ||Y^H B||_F^2 against the Daleckii-Krein
-    closed form built from the planted eigenvectors, on the GPU with torch."""
+@pytest.mark.parametrize("cplx", [True, False])
+def test_filter_adjoint_full_size_daleckii_krein(pk, cplx):
+    """Differentiation workload size (n=8000 complex128 and float64,
+    nev+nex=260 columns, degree 20): the gradient of ||Y^H B||_F^2 against
+    the Daleckii-Krein closed form built from the planted eigenvectors, on
+    the GPU with torch."""
     import torch
-    announce("filter adjoint n=8000 vs Daleckii-Krein")
-    p = gen.make_uniform(n=8000, nev=200, nex=60, cfg=gen.CFG_DIFF8K)
-    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, True)
+    announce(f"filter adjoint n=8000 vs Daleckii-Krein cplx={cplx}")
+    p = gen.make_uniform(n=8000, nev=200, nex=60, cplx=cplx, cfg=gen.CFG_DIFF8K)
+    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, cplx)
     b_sup, mu_1, mu_ne, m = 1.05, -1.0, -0.9, 20
     deg = np.full(260, m, dtype=np.int32)
     H = to_gpu(p.H).requires_grad_(True)
@@ -169,7 +171,7 @@ def test_filter_adjoint_full_size_daleckii_krein(pk):
         F = np.where(np.abs(dl) > 1e-7, (pv[:, None] - pv[None, :]) / dl,
                      0.5 * (dp[:, None] + dp[None, :]))
     q = to_gpu(p.Q)
-    Ft = to_gpu(F).to(torch.complex128)
+    Ft = to_gpu(F).to(q.dtype)
     gY = 2.0 * Bt @ (Bt.mH @ Y.detach())
     M = (q.mH @ gY) @ (X0.mH @ q)
     G_ref = q @ (Ft * M) @ q.mH
@@ -235,14 +237,16 @@ def test_eigvec_autograd_matches_finite_differences(pk, cplx):
         assert abs(fd - an) <= 1e-6 * max(abs(an), np.linalg.norm(G) * 1e-3), (fd, an)
 
 
-def test_eigvec_adjoint_full_size_planted(pk):
-    """Differentiation workload size (n=8000 complex128, 200 eigenvectors):
-    the adjoint of ||V^H B||_F^2 against the first-order formula evaluated
-    with torch from the planted eigendecomposition (all 8000 pairs)."""
+@pytest.mark.parametrize("cplx", [True, False])
+def test_eigvec_adjoint_full_size_planted(pk, cplx):
+    """Differentiation workload size (n=8000 complex128 and float64, 200
+    eigenvectors): the adjoint of ||V^H B||_F^2 against the first-order
+    formula evaluated with torch from the planted eigendecomposition (all
+    8000 pairs)."""
     import torch
-    announce("eigvec adjoint n=8000 vs planted first-order formula")
-    p = gen.make_uniform(n=8000, nev=200, nex=60, cfg=gen.CFG_DIFF8K)
-    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, True)
+    announce(f"eigvec adjoint n=8000 vs planted first-order formula cplx={cplx}")
+    p = gen.make_uniform(n=8000, nev=200, nex=60, cplx=cplx, cfg=gen.CFG_DIFF8K)
+    _, B = gen.loss_weights(gen.CFG_DIFF8K, 200, 16, 8000, cplx)
     Q = to_gpu(p.Q)
     lam = torch.from_numpy(p.lam).cuda()
     V = Q[:, :200].contiguous()
@@ -262,3 +266,49 @@ def test_eigvec_adjoint_full_size_planted(pk):
     err = float(torch.linalg.matrix_norm(dH - ref) / torch.linalg.matrix_norm(ref))
     print(f"[gpu-case] eigvec adjoint n=8000: {its} CG iterations, rel err {err:.2e}", flush=True)
     assert err < 1e-6, err
+
+
+@pytest.mark.parametrize("cplx", [True, False])
+def test_differentiation_workload_finite_differences(pk, cplx):
+    """The differentiation workload end to end (n=8000, nev=200, nex=60):
+    L = sum_i w_i lambda_i + ||Y^H B||_F^2 with lambda from the solve and Y
+    the filtered start block at frozen bounds and degrees, gradient by the
+    library's adjoints through autograd, against central differences
+    (h = 1e-6) along two Hermitian directions: one built from B (so the
+    directional derivative is a sizeable part of ||G||) and one Gaussian.
+    The differences carry the forward evaluation's rounding over h, so the
+    bar is 1e-6 of max(|derivative|, 1e-3 ||G||_F)."""
+    import torch
+    announce(f"differentiation workload FD n=8000 cplx={cplx}")
+    n, nev, nex, tol, m = 8000, 200, 60, 1e-10, 20
+    p = gen.make_uniform(n=n, nev=nev, nex=nex, cplx=cplx, cfg=gen.CFG_DIFF8K)
+    w, B = gen.loss_weights(gen.CFG_DIFF8K, nev, 16, n, cplx)
+    Hd, V0, S = to_gpu(p.H), to_gpu(p.V0), to_gpu(p.S)
+    Bt, wt = to_gpu(B), to_gpu(w)
+    _, _, _, st = pk.chase_solve(Hd, nev, nex, tol, m, V0, S)
+    frozen = (st["b_sup"], st["mu_1"], st["mu_ne"])
+    deg = np.full(nev + nex, m, dtype=np.int32)
+
+    def loss(Hx):
+        lam, _ = pk.chase_eigh(Hx, nev, nex, tol, m, V0, S)
+        Y = pk.filtered_block(Hx, V0, deg, *frozen)
+        return (wt * lam).sum() + torch.linalg.matrix_norm(Y.mH @ Bt) ** 2
+
+    H = Hd.clone().requires_grad_(True)
+    loss(H).backward()
+    G = to_np(H.grad)
+    gnorm = np.linalg.norm(G)
+    g = np.random.Generator(np.random.PCG64(930 + cplx))
+    c = gen.gaussian(g, (16, 16), cplx)
+    E1 = B @ c @ B.conj().T
+    E2 = gen.gaussian(g, (n, n), cplx)
+    h = 1e-6
+    for E in (E1, E2):
+        E = (E + E.conj().T) / 2
+        E /= np.linalg.norm(E)
+        Et = to_gpu(E)
+        with torch.no_grad():
+            fd = (float(loss(Hd + h * Et)) - float(loss(Hd - h * Et))) / (2 * h)
+        an = directional(G, E)
+        announce(f"  FD {fd:.10e}  adjoint {an:.10e}  rel {abs(fd - an) / abs(an):.2e}")
+        assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gnorm), (fd, an, gnorm)
