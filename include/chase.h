@@ -118,7 +118,15 @@ typedef struct chase_opts {
                           defects go to chase_stats.  Costs one extra pass
                           over H and one Gram product per iteration
                           (default 0)                                       */
-  int reserved[3];
+  int adjoint_reserve; /* > 0: chase_create also allocates what the adjoints
+                          need (the eigenvector adjoint's two n x (nev+nex)
+                          blocks and a filter tape of adjoint_reserve steps
+                          over nev+nex columns), so that chase_filter with
+                          record_tape = 1 (degrees <= adjoint_reserve) and
+                          chase_eigvec_adjoint allocate nothing; counted by
+                          chase_workspace_bytes.  0 (default): they
+                          allocate on first use                             */
+  int reserved[2];
 } chase_opts;
 
 typedef struct chase_stats {
@@ -228,8 +236,10 @@ chase_status chase_lanczos_noalloc(chase_dtype dtype, const void* H_dev, int64_t
  * prec: chase_prec (CHASE_PREC_BF16X3 needs a handle created with
  * filter_prec = CHASE_PREC_BF16X3, else CHASE_ERR_ARG; H_dev is split on
  * every call).  record_tape=1 keeps every intermediate block on the
- * device for chase_filter_adjoint (needs tape memory; CHASE_ERR_NOMEM if it
- * does not fit).  matvecs (may be NULL) receives the matrix-vector count. */
+ * device for chase_filter_adjoint (needs tape memory, (max degree + 1) n k
+ * elements: reserved at creation by chase_opts.adjoint_reserve, else
+ * allocated here; CHASE_ERR_NOMEM if it does not fit).  matvecs (may be
+ * NULL) receives the matrix-vector count. */
 chase_status chase_filter(chase_handle_t handle, const void* H_dev, int64_t ldh,
                           void* X_dev, int64_t ldx, int k, const int* degrees_host,
                           double b_sup, double mu_1, double mu_ne, int prec,
@@ -301,8 +311,9 @@ chase_status chase_eigval_adjoint(chase_handle_t handle, const void* V_dev,
  * GEMM per iteration, until every column's residual is below tol times its
  * initial residual (checked every 10 iterations); iterations (may be NULL)
  * receives the count.  CHASE_ERR_NOCONV after max_iter iterations, with
- * dH_dev unchanged.  Uses the handle's workspace (1 <= m <= nev+nex); the
- * first call allocates two more n x (nev+nex) blocks in the handle. */
+ * dH_dev unchanged.  Uses the handle's workspace (1 <= m <= nev+nex) and
+ * two more n x (nev+nex) blocks, reserved at creation by
+ * chase_opts.adjoint_reserve, else allocated by the first call. */
 chase_status chase_eigvec_adjoint(chase_handle_t handle, const void* H_dev, int64_t ldh,
                                   const void* V_dev, int64_t ldv, int m,
                                   const double* lambda_host, const void* G_dev, int64_t ldg,

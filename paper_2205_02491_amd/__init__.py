@@ -47,7 +47,8 @@ class Opts(ctypes.Structure):
                 ("filter_prec", ctypes.c_int), ("switch_tol", ctypes.c_double),
                 ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
                 ("fp64_tail", ctypes.c_int), ("seed", ctypes.c_int),
-                ("debug", ctypes.c_int), ("reserved", ctypes.c_int * 3)]
+                ("debug", ctypes.c_int), ("adjoint_reserve", ctypes.c_int),
+                ("reserved", ctypes.c_int * 2)]
 
 
 class Stats(ctypes.Structure):

@@ -51,7 +51,8 @@ def build(verbose: bool = False) -> str:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
     tmp = OUT + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", f"-Wl,-rpath,{ROCM}/lib"]
+           f"-L{ROCM}/lib", "-lrocsolver", "-lrocblas", "-lrocprofiler-sdk-roctx",
+           f"-Wl,-rpath,{ROCM}/lib"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

@@ -6,6 +6,7 @@
 // buffers before the main loop).  Per iteration the host only sees a few KB:
 // the QR pivots, the Ritz values and the residual norms.
 #include <rocblas/rocblas.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
@@ -99,6 +100,21 @@ char* noalloc_scratch() {
   return static_cast<char*>(g_scratch_ptr[dev]);
 }
 
+// roctx range around a phase of the solve: named spans on the timeline of
+// a profiler that records markers (rocprofv3 --marker-trace); a few hundred
+// nanoseconds each otherwise.
+struct Range {
+  bool open = true;
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  void end() {
+    if (open) roctxRangePop();
+    open = false;
+  }
+  ~Range() { end(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
+
 using clk = std::chrono::steady_clock;
 double secs(clk::time_point a, clk::time_point b) {
   return std::chrono::duration<double>(b - a).count();
@@ -146,7 +162,7 @@ size_t splitk_ws_elems(int ne) {
 constexpr int kMaxDegree = 1000;  // largest filter degree any entry point accepts
 
 struct Sizes {
-  size_t blocks, small, lz, ws, h32, total;
+  size_t blocks, small, lz, ws, h32, adj, total;
   int lz_splits;
 };
 
@@ -167,7 +183,11 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
             2 * s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) + s8_tail_bytes(cplx) +
             (size_t)n * ne * esz;
   s.small += (size_t)(kMaxDegree + 1) * ne * 8;
-  s.total = s.blocks + s.ws + s.small + s.lz + s.h32;
+  // adjoint buffers reserved up front: the eigenvector adjoint's two blocks
+  // and a filter tape of adjoint_reserve steps over ne columns
+  if (o.adjoint_reserve > 0)
+    s.adj = 2 * (size_t)n * ne * esz + (size_t)(o.adjoint_reserve + 1) * n * ne * esz;
+  s.total = s.blocks + s.ws + s.small + s.lz + s.h32 + s.adj;
   return s;
 }
 
@@ -176,6 +196,8 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.deg_extra >= 0, "deg_extra < 0");
   CHASE_REQUIRE(o.lanczos_steps >= 1 && o.lanczos_steps <= 200, "lanczos_steps out of range");
   CHASE_REQUIRE(o.lanczos_vecs >= 1 && o.lanczos_vecs <= 8, "lanczos_vecs out of range [1,8]");
+  CHASE_REQUIRE(o.adjoint_reserve >= 0 && o.adjoint_reserve <= kMaxDegree,
+                "adjoint_reserve out of range [0, 1000]");
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
   CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
   CHASE_REQUIRE(o.fp64_tail >= -1 && o.fp64_tail <= kMaxDegree, "fp64_tail out of range [-1,1000]");
@@ -750,6 +772,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   const bool cplx = h->cplx;
   const chase_opts& o = h->opts;
   chase_stats stats{};
+  Range r_solve("chase_solve");
   auto T0 = clk::now();
   const int deg0 = degree + (degree & 1);
 
@@ -777,8 +800,10 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   // Lanczos spectral bounds
   const int steps = (int)std::min<int64_t>(o.lanczos_steps, n);
   std::vector<double> lz_a, lz_b;
+  Range r_lz("lanczos");
   Bounds bd = do_lanczos(h, H, ldh, S, o.lanczos_vecs, steps, &lz_a, &lz_b, nullptr, st,
                          &stats.t_lanczos_gemv);
+  r_lz.end();
   stats.lanczos_gemv_launches = steps;
   stats.lanczos_gemv_bytes = (double)steps * (double)n * (double)n * (double)h->esz;
   auto T1 = clk::now();
@@ -959,6 +984,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     stats.iterations = it + 1;
     const int ka = ne - L;
     // ---- filter (FP64 group first, then the low-precision group)
+    Range r_f("filter");
     auto F0 = clk::now();
     int n64 = 0;
     while (n64 < ka && !low[L + n64]) ++n64;
@@ -977,18 +1003,23 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
                           ftlo, st);
     }
     auto F1 = clk::now();
+    r_f.end();
     stats.t_filter += secs(F0, F1);
     debug_check("the filter", L, false);
     // ---- QR of [Y V]
     F1 = clk::now();
+    Range r_qr("qr");
     qr_step(h, h->V, n, ne, L, h->W, &stats, st);
+    r_qr.end();
     auto Q1 = clk::now();
     stats.t_qr += secs(F1, Q1);
     debug_check("QR", 0, true);
     // ---- Rayleigh-Ritz + residuals on the active part
+    Range r_rr("rayleigh_ritz_residual");
     rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
             &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n,
             &stats.t_rr_eig);
+    r_rr.end();
     debug_check("Rayleigh-Ritz", L, false);
     if (after_rr(it, ka, n64)) break;
   }
@@ -1205,6 +1236,10 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
+    if (o.adjoint_reserve > 0) {
+      h->adj = dev_alloc(h, 2 * (size_t)n * ne * h->esz);
+      ensure_tape(h, (int)ne, o.adjoint_reserve);
+    }
     rb_check(rocblas_create_handle(&h->rb), "rocblas_create_handle");
     CHASE_HIP(hipEventCreate(&h->eig_ev[0]));
     CHASE_HIP(hipEventCreate(&h->eig_ev[1]));

@@ -40,7 +40,7 @@ def test_default_opts():
     o = pk.default_opts()
     assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
             o.max_iter, o.filter_prec, o.initial_rr, o.fp64_tail) == (36, 2, 1, 25, 4, 50, 0, 0, -1)
-    assert (o.seed, o.debug) == (0, 0)
+    assert (o.seed, o.debug, o.adjoint_reserve) == (0, 0, 0)
 
 
 @pytest.mark.parametrize("struct", ["chase_opts", "chase_stats"])
@@ -99,6 +99,14 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
         # the two-term form keeps the same splits (it only skips MFMAs)
         o2 = pk.default_opts(filter_prec=pk.PREC_BF16X2)
         assert pk.chase_workspace_bytes(n, nev, nex, cplx=cplx, opts=o2) == b3
+    # adjoint buffers reserved at creation: two n x ne blocks for the
+    # eigenvector adjoint and a tape of (steps + 1) n x ne blocks
+    for cplx in (True, False):
+        n, ne, esz = 8000, 260, (16 if cplx else 8)
+        base = pk.chase_workspace_bytes(n, 200, 60, cplx=cplx)
+        res = pk.chase_workspace_bytes(n, 200, 60, cplx=cplx,
+                                       opts=pk.default_opts(adjoint_reserve=20))
+        assert res - base == (2 + 21) * n * ne * esz
     assert pk.chase_workspace_bytes(10, 8, 4) == 0      # nev + nex > n
     assert pk.chase_workspace_bytes(10, 0, 4) == 0
 

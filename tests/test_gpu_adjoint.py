@@ -312,3 +312,33 @@ def test_differentiation_workload_finite_differences(pk, cplx):
         an = directional(G, E)
         announce(f"  FD {fd:.10e}  adjoint {an:.10e}  rel {abs(fd - an) / abs(an):.2e}")
         assert abs(fd - an) <= 1e-6 * max(abs(an), 1e-3 * gnorm), (fd, an, gnorm)
+
+
+def test_adjoints_with_reserved_buffers_match(pk):
+    """A handle created with adjoint_reserve holds the filter tape and the
+    eigenvector adjoint's blocks from creation; the adjoints computed with it
+    equal those of a handle that allocates them on first use."""
+    import torch
+    announce("adjoints with buffers reserved at creation")
+    n, k, m, nev = 400, 30, 12, 10
+    g = np.random.Generator(np.random.PCG64(77))
+    lam = gen.spectrum_uniform_iid(n, g)
+    q = gen.haar(n, g, True)
+    H = to_gpu(gen.planted(lam, q))
+    X0 = to_gpu(gen.gaussian(g, (n, k), True))
+    gY = to_gpu(gen.gaussian(g, (n, k), True))
+    Gv = to_gpu(gen.gaussian(g, (n, nev), True))
+    V = to_gpu(q[:, :nev])
+    deg = np.full(k, m, dtype=np.int32)
+    out = []
+    for reserve in (0, m):
+        h = pk.Handle(n, k - 5, 5, H.dtype, pk.default_opts(adjoint_reserve=reserve))
+        pk.chase_filter(H, X0, deg, 1.05, -1.0, -0.5, record_tape=True, handle=h)
+        dF = torch.zeros_like(H)
+        pk.chase_filter_adjoint(H, gY, dF, h)
+        dV = torch.zeros_like(H)
+        pk.chase_eigvec_adjoint(H, V, lam[:nev], Gv, dV, handle=h, tol=1e-12)
+        out.append((to_np(dF), to_np(dV)))
+        h.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
