@@ -858,8 +858,15 @@ void fill_gaussian(bool cplx, void* X, int64_t ldx, int64_t n, int64_t k, uint64
                    uint64_t stream_id, hipStream_t st) {
   if (n <= 0 || k <= 0) return;
   const int W = cplx ? 2 : 1;
-  // one key per (seed, stream): the counters of different streams never meet
-  const uint64_t key = (seed * 0x100000001B3ull + stream_id) << 40;
+  // one key per (seed, stream), scrambled by the same (bijective) finaliser:
+  // distinct pairs give distinct keys, and two streams' counter ranges
+  // (below 2^41 for any block the library draws) overlap with probability
+  // about 2^-22
+  uint64_t z = seed ^ (stream_id << 32) ^ 0xD1B54A32D192ED03ull;
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  const uint64_t key = z ^ (z >> 31);
   hipLaunchKernelGGL(fill_gaussian_k, dim3(blocks_for(n * W * k, TPB * 4, 65536)), dim3(TPB), 0,
                      st, static_cast<double*>(X), ldx * W, n * W, k, key);
   CHASE_HIP(hipGetLastError());
