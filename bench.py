@@ -13,9 +13,11 @@ algorithmic TFLOP/s against the FP64 MFMA peak (roofline), the Lanczos block
 GEMV's GB/s against the HBM peak, the mixed-precision solves on the same
 matrix, the CPU oracle timed on the same host (its solve estimated from timed
 pieces of the same matrix, and a complete small solve beside the library's),
-and a second block on the mixed-precision workload: n=30000 complex128,
-lowest 2000 eigenvalues those of the (1-2-1) matrix of order 30000, the rest
-uniform up to 10, nev=1500, nex=500, solved once in each filter mode.
+the vendor's own GEMM rates on the same GPU (hipBLASLt BF16, rocBLAS FP64
+and complex128) as the practical ceiling beside the published peaks, and a
+second block on the mixed-precision workload: n=30000 complex128, lowest 2000
+eigenvalues those of the (1-2-1) matrix of order 30000, the rest uniform up
+to 10, nev=1500, nex=500, solved once in each filter mode.
 """
 from __future__ import annotations
 
