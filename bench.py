@@ -62,6 +62,18 @@ WORKLOADS = {
     "cluster121_30k": dict(kind="cluster121", n=30000, nev=1500, nex=500, deg=20, tol=1e-10),
     "reflectors100k": dict(kind="reflectors", n=100000, nev=2000, nex=600, deg=20, tol=1e-10),
     "diff8k": dict(kind="uniform", n=8000, nev=200, nex=60, deg=20, tol=1e-10),
+    "table2": dict(kind="table2", n=20000, nev=1500, nex=500, deg=20, tol=1e-10),
+}
+
+# The paper's eigen-type tests (Table 2, GPU rows: one node of 4 NVIDIA A100,
+# FP64, real symmetric n=20000, nev=1500, nex=500): iterations, Matvecs and
+# seconds for All, Lanczos, Filter, QR, RR and Resid, as context for the
+# table2 workload (the same matrix types on one MI355X).
+PAPER_TABLE2_GPU = {
+    "121": (13, 466614, 31.39, 0.58, 14.38, 2.59, 8.41, 5.24),
+    "geometric": (8, 285192, 18.57, 0.58, 8.76, 1.58, 4.58, 2.96),
+    "uniform": (5, 163562, 11.79, 0.58, 5.06, 1.00, 3.11, 1.96),
+    "wilkinson": (8, 246924, 17.22, 0.57, 7.63, 1.59, 4.45, 2.90),
 }
 
 
@@ -565,6 +577,36 @@ def mixed_workload_block(pk, precs, steps, warmup):
     return out
 
 
+def table2_block(pk, precs, steps, warmup):
+    """The paper's matrix types (Table 1: Uniform, Geometric, (1-2-1),
+    Wilkinson spectra) as dense real symmetric n=20000 matrices Q diag(lam)
+    Q^T with a Haar Q, nev=1500, nex=500, degree 20, tol 1e-10: one MI355X
+    beside the paper's one node of 4 A100 (Table 2, FP64)."""
+    import torch
+
+    import gen
+
+    wl = WORKLOADS["table2"]
+    out = {}
+    for kind in ("uniform", "geometric", "121", "wilkinson"):
+        t0 = time.perf_counter()
+        prob = gen.make_torch(kind, wl["n"], wl["nev"], wl["nex"], device="cuda", cplx=False,
+                              cfg=gen.CFG_TABLE2, lam=gen.spectrum_table1(kind, wl["n"]))
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        log(f"generated table2 {kind} in {time.perf_counter() - t0:.1f} s")
+        res = time_modes(pk, prob, wl, precs, steps, warmup, f"table2 {kind}")
+        fp64_s = res["fp64"]["solve_s"] if "fp64" in res else None
+        it, mv, *secs = PAPER_TABLE2_GPU[kind]
+        out[kind] = {p: mode_summary(res[p], p, fp64_s) for p in precs}
+        out[kind]["paper_gpu_node"] = {
+            "iterations": it, "matvecs": mv,
+            "seconds": dict(zip(("all", "lanczos", "filter", "qr", "rr", "resid"), secs))}
+        del prob, res
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -628,6 +670,20 @@ def main():
     n, nev, nex = wl["n"], wl["nev"], wl["nex"]
     if args.workload == "diff8k":
         print(json.dumps(bench_diff(args, wl)), flush=True)
+        return
+    if args.workload == "table2":
+        precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"]}.get(
+            args.prec, [args.prec])
+        if "fp64" not in precs:
+            precs = ["fp64"] + precs
+        t2 = table2_block(pk, precs, args.steps, args.warmup)
+        print(json.dumps({"metric": "solve s per matrix type (Table 2 suite, n=20000 float64)",
+                          "unit": "s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                          "higher_is_better": False, "data": "synthetic (Table 1 spectra, Haar Q)",
+                          "config": {"workload": "table2", "n": n, "nev": nev, "nex": nex,
+                                     "degree": wl["deg"], "tol": wl["tol"]},
+                          "value": t2["121"]["fp64"]["solve_s"], "vs_baseline": None,
+                          "table2": t2}), flush=True)
         return
     t0 = time.perf_counter()
     if wl["kind"] == "reflectors":

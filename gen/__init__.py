@@ -25,7 +25,7 @@ BASE_SEED = 220502491
 SLOT_Q, SLOT_LAMBDA, SLOT_V0, SLOT_S, SLOT_W, SLOT_B = range(6)
 
 # configuration indices used to derive seeds
-CFG_SMALL, CFG_GEO20K, CFG_MIXED30K, CFG_HUGE100K, CFG_DIFF8K = range(5)
+CFG_SMALL, CFG_GEO20K, CFG_MIXED30K, CFG_HUGE100K, CFG_DIFF8K, CFG_TABLE2 = range(6)
 
 
 def rng(cfg: int, slot: int) -> np.random.Generator:
@@ -106,6 +106,25 @@ def tridiag_wilkinson(n: int):
 
 def dense_from_tridiag(d: np.ndarray, e: np.ndarray) -> np.ndarray:
     return np.diag(d) + np.diag(e, 1) + np.diag(e, -1)
+
+
+def spectrum_table1(kind: str, n: int) -> np.ndarray:
+    """Ascending eigenvalues of the paper's matrix types (Table 1): Uniform
+    and Geometric (d_max = 1, eps = 1e-4), and the spectra of the (1-2-1)
+    and Wilkinson tridiagonal matrices of order n (the (1-2-1) one in closed
+    form, the Wilkinson one from LAPACK's tridiagonal eigensolver)."""
+    if kind == "uniform":
+        return table1_uniform(n)
+    if kind == "geometric":
+        return table1_geometric(n)
+    if kind == "121":
+        k = np.arange(1, n + 1, dtype=np.float64)
+        return 2.0 - 2.0 * np.cos(np.pi * k / (n + 1))
+    if kind == "wilkinson":
+        import scipy.linalg
+        d, e = tridiag_wilkinson(n)
+        return scipy.linalg.eigvalsh_tridiagonal(d, e)
+    raise ValueError(kind)
 
 
 # ---------------------------------------------------------------- problems
@@ -194,16 +213,19 @@ def loss_weights(cfg: int, nev: int, ncols_b: int, n: int, cplx: bool):
 
 # ------------------------------------------------------- device-side draws
 def make_torch(kind: str, n: int, nev: int, nex: int, device="cuda", cplx=True,
-               cfg=None, n_lanczos=4, deg=20, tol=1e-10):
+               cfg=None, n_lanczos=4, deg=20, tol=1e-10, lam=None):
     """Large workloads drawn on the device with torch (seeded torch.Generator),
     the same recipe as the numpy builders: Haar Q from the QR of a Gaussian
     with phases fixed, H = Q diag(lam) Q^H symmetrised. Returns a dict of
-    torch tensors in row-major layout plus the planted spectrum (numpy)."""
+    torch tensors in row-major layout plus the planted spectrum (numpy).
+    ``lam`` (ascending) overrides the kind's spectrum."""
     import torch
 
     if cfg is None:
         cfg = {"geometric": CFG_GEO20K, "cluster121": CFG_MIXED30K, "uniform": CFG_DIFF8K}[kind]
-    if kind == "geometric":
+    if lam is not None:
+        lam = np.asarray(lam, dtype=np.float64)
+    elif kind == "geometric":
         lam = spectrum_geometric_low(n, rng(cfg, SLOT_LAMBDA), 1200 if n == 20000 else (nev + nex) * 12 // 13)
     elif kind == "cluster121":
         lam = spectrum_121_cluster(n, rng(cfg, SLOT_LAMBDA), nev + nex)
