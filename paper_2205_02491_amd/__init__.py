@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libchase.so")
 
 C128, F64 = 0, 1
 PREC_FP64, PREC_FP32, PREC_BF16X3, PREC_BF16X2 = 0, 1, 2, 3
+EIG_AUTO, EIG_LIBRARY, EIG_JACOBI = 0, 1, 2
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NOCONV, ERR_NUMERIC = range(6)
 _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
            4: "CHASE_ERR_NOCONV", 5: "CHASE_ERR_NUMERIC"}
@@ -29,7 +30,7 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
             "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
             "chase_filter_ritz", "chase_qr",
-            "chase_rayleigh_ritz", "chase_eigval_adjoint", "chase_eigvec_adjoint",
+            "chase_rayleigh_ritz", "chase_heev", "chase_eigval_adjoint", "chase_eigvec_adjoint",
             "chase_filter_adjoint", "chase_filter_coefficients", "chase_spectral_bounds",
             "chase_degrees", "chase_last_error"]
 
@@ -48,7 +49,7 @@ class Opts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
                 ("fp64_tail", ctypes.c_int), ("seed", ctypes.c_int),
                 ("debug", ctypes.c_int), ("adjoint_reserve", ctypes.c_int),
-                ("reserved", ctypes.c_int * 2)]
+                ("eig_solver", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
 
 
 class Stats(ctypes.Structure):
@@ -66,7 +67,8 @@ class Stats(ctypes.Structure):
                 ("t_filter_kernels_low", ctypes.c_double),
                 ("filter_launches_low", ctypes.c_int64), ("fp64_tail", ctypes.c_int),
                 ("debug_herm_defect", ctypes.c_double),
-                ("debug_orth_defect", ctypes.c_double), ("t_rr_eig", ctypes.c_double)]
+                ("debug_orth_defect", ctypes.c_double), ("t_rr_eig", ctypes.c_double),
+                ("eig_jacobi_calls", ctypes.c_int), ("eig_jacobi_sweeps", ctypes.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -111,6 +113,8 @@ def lib():
     L.chase_qr.restype = ci
     L.chase_rayleigh_ritz.argtypes = [vp, vp, i64, vp, i64, ci, cd, pd, pd, vp]
     L.chase_rayleigh_ritz.restype = ci
+    L.chase_heev.argtypes = [vp, vp, i64, ci, ci, pd, pi, vp]
+    L.chase_heev.restype = ci
     L.chase_eigval_adjoint.argtypes = [vp, vp, i64, ci, pd, vp, i64, vp]
     L.chase_eigval_adjoint.restype = ci
     L.chase_filter_adjoint.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
@@ -452,6 +456,32 @@ def chase_rayleigh_ritz(H, Q, norm_scale=1.0, handle=None):
     return ritz, buf.mH, res
 
 
+def chase_heev(G, method=EIG_AUTO, handle=None):
+    """Dense Hermitian eigensolve of G (k x k) with the eigensolver of the
+    library's Rayleigh-Ritz step (method: EIG_AUTO, EIG_LIBRARY or
+    EIG_JACOBI).  Returns (eigenvalues numpy[k] ascending, W tensor (k, k)
+    with the eigenvectors as columns, Jacobi sweeps (0 when the library's
+    divide and conquer ran)).  G is not modified."""
+    import torch
+    _check_square(G)
+    k = G.shape[0]
+    if handle is None:
+        handle = Handle(max(k, 2), max(1, k - 1), 1, G.dtype)
+    if handle.cplx != (G.dtype == torch.complex128):
+        raise ValueError("handle and G differ in element type")
+    if not 1 <= k <= handle.nev + handle.nex:
+        raise ValueError(f"k={k} exceeds the handle's nev+nex={handle.nev + handle.nex}")
+    # the row-major buffer of G is the column-major buffer of conj(G): same
+    # eigenvalues, conjugated eigenvectors
+    buf = G.resolve_conj().clone(memory_format=torch.contiguous_format)
+    ev = np.zeros(k)
+    sw = ctypes.c_int()
+    _check(lib().chase_heev(handle.ptr, _dev(buf), k, k, int(method),
+                            ev.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                            ctypes.byref(sw), _stream()))
+    return ev, buf.mH, sw.value
+
+
 def chase_eigval_adjoint(V, g, dH, handle=None):
     """dH += V diag(g) V^H (in place on the torch tensor dH, n x n)."""
     if V.dim() != 2:
@@ -567,7 +597,7 @@ from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
            "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
            "chase_filter_ritz", "chase_qr",
-           "chase_rayleigh_ritz",
+           "chase_rayleigh_ritz", "chase_heev",
            "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint",
            "chase_filter_coefficients", "chase_spectral_bounds", "chase_degrees", "ChaseEigh",
            "chase_eigh",

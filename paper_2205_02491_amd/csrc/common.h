@@ -214,6 +214,23 @@ void cg_dir(bool cplx, void* P, const void* R, int64_t ld, int64_t n, int64_t k,
 void sym_divdiff(bool cplx, const void* M, int64_t ldm, const double* lam, int64_t k, void* E,
                  int64_t lde, hipStream_t st);
 
+// ------------------------------------------------------------------ Jacobi eigensolver
+// Device workspace of the block Jacobi eigensolver for orders up to kmax.
+size_t jacobi_ws_bytes(bool cplx, int kmax);
+// Squared Frobenius norms of a k x k matrix: off2 off the diagonal, dia2 on it
+// (synchronises the stream).
+void jacobi_norms(bool cplx, const void* G, int64_t ldg, int k, void* ws, int kmax, double* off2,
+                  double* dia2, hipStream_t st);
+// Eigen-decomposition of the Hermitian k x k G (destroyed) by block-cyclic
+// Jacobi until off2 <= tol^2 (off2 + dia2) (the norms of G on entry, from
+// jacobi_norms); V (k x k) is scratch, W (may be G) receives the
+// eigenvectors and d_evals / evals_host the eigenvalues, ascending; d_perm
+// holds k ints.  Returns the sweeps; throws CHASE_ERR_NUMERIC after
+// max_sweeps.
+int jacobi_heev(bool cplx, void* G, int64_t ldg, int k, void* V, int64_t ldv, void* W,
+                int64_t ldw, double* d_evals, int* d_perm, void* ws, int kmax, double* evals_host,
+                hipStream_t st, double off2, double dia2, double tol, int max_sweeps);
+
 // ------------------------------------------------------------------ Lanczos
 struct LanczosBufs {
   void* q_prev;    // n x nv

@@ -59,6 +59,7 @@ struct chase_handle_s {
   void* tape = nullptr;
   size_t tape_bytes = 0;
   void* adj = nullptr;  // eigenvector adjoint: two n x ne blocks (first use; in allocs)
+  void* jac_ws = nullptr;  // Jacobi eigensolver workspace (orders up to ne)
   std::vector<int> tape_deg;
   std::vector<Coef> tape_coef;
   int tape_k = 0;
@@ -183,6 +184,7 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
             2 * s8_bytes(cplx, n, s8_pad(ne, S8_COLS_B)) + s8_tail_bytes(cplx) +
             (size_t)n * ne * esz;
   s.small += (size_t)(kMaxDegree + 1) * ne * 8;
+  s.small += jacobi_ws_bytes(cplx, (int)ne);
   // adjoint buffers reserved up front: the eigenvector adjoint's two blocks
   // and a filter tape of adjoint_reserve steps over ne columns
   if (o.adjoint_reserve > 0)
@@ -201,6 +203,9 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
   CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
   CHASE_REQUIRE(o.fp64_tail >= -1 && o.fp64_tail <= kMaxDegree, "fp64_tail out of range [-1,1000]");
+  CHASE_REQUIRE(o.eig_solver == CHASE_EIG_AUTO || o.eig_solver == CHASE_EIG_LIBRARY ||
+                    o.eig_solver == CHASE_EIG_JACOBI,
+                "unknown eig_solver");
   CHASE_REQUIRE(o.filter_prec == CHASE_PREC_FP64 || o.filter_prec == CHASE_PREC_FP32 ||
                     o.filter_prec == CHASE_PREC_BF16X3 || o.filter_prec == CHASE_PREC_BF16X2,
                 "unknown filter_prec");
@@ -621,20 +626,31 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
 }
 
 // ------------------------------------------------------------------ Rayleigh-Ritz + residual
-// Q (n x k, ld ldq) orthonormal -> Ritz vectors; ritz/res on the device
-// (h->d_evals, h->d_res).  Scratch: P (n x k, ld n), Zb (n x k, ld n).
-void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq, int k,
-             double norm_scale, void* P, void* Zb, double* t_rr, double* t_resid,
-             hipStream_t st, void* Rout = nullptr, int64_t ldr = 0, double* t_eig = nullptr) {
-  const int64_t n = h->n;
-  const bool cplx = h->cplx;
-  auto t0 = clk::now();
-  // P = H Q   (the HEMM of the Rayleigh-Ritz step)
-  gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
-  // G = Q^H P, exactly Hermitian
-  gram(h, Q, ldq, P, n, n, k, k, h->G, k, true, st);
-  if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[0], st));
-  if (cplx)
+// The automatic choice runs Jacobi when the off-diagonal part of the
+// projected matrix has at most this fraction of its Frobenius norm.
+constexpr double kAutoJacobiOff = 0.05;
+constexpr double kJacobiTol = 1e-14;
+constexpr int kJacobiMaxSweeps = 60;
+
+// Dense eigensolve of the Hermitian k x k matrix h->G (ld k): eigenvalues
+// ascending to h->d_evals, eigenvectors over h->G.  Returns the Jacobi
+// sweeps (-1: the library's divide and conquer ran).
+int small_eig(chase_handle_s* h, int k, int method, hipStream_t st) {
+  double off2 = 0.0, dia2 = 0.0;
+  if (method != CHASE_EIG_LIBRARY) {
+    jacobi_norms(h->cplx, h->G, k, k, h->jac_ws, h->ne, &off2, &dia2, st);
+    if (method == CHASE_EIG_AUTO)
+      method = off2 <= kAutoJacobiOff * kAutoJacobiOff * (off2 + dia2) ? CHASE_EIG_JACOBI
+                                                                        : CHASE_EIG_LIBRARY;
+  }
+  if (method == CHASE_EIG_JACOBI) {
+    // callers check the library solver's info word: Jacobi reports by throwing
+    fill_zero(h->d_info, sizeof(int), st);
+    std::vector<double> ev(k);
+    return jacobi_heev(h->cplx, h->G, k, k, h->R, k, h->G, k, h->d_evals, h->d_perm, h->jac_ws,
+                       h->ne, ev.data(), st, off2, dia2, kJacobiTol, kJacobiMaxSweeps);
+  }
+  if (h->cplx)
     rb_check(rocsolver_zheevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
                               static_cast<rocblas_double_complex*>(h->G), k, h->d_evals, h->d_E,
                               h->d_info),
@@ -643,6 +659,28 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
     rb_check(rocsolver_dsyevd(h->rb, rocblas_evect_original, rocblas_fill_upper, k,
                               static_cast<double*>(h->G), k, h->d_evals, h->d_E, h->d_info),
              "dsyevd");
+  return -1;
+}
+
+// Q (n x k, ld ldq) orthonormal -> Ritz vectors; ritz/res on the device
+// (h->d_evals, h->d_res).  Scratch: P (n x k, ld n), Zb (n x k, ld n).
+void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq, int k,
+             double norm_scale, void* P, void* Zb, double* t_rr, double* t_resid,
+             hipStream_t st, void* Rout = nullptr, int64_t ldr = 0, double* t_eig = nullptr,
+             chase_stats* stats = nullptr) {
+  const int64_t n = h->n;
+  const bool cplx = h->cplx;
+  auto t0 = clk::now();
+  // P = H Q   (the HEMM of the Rayleigh-Ritz step)
+  gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
+  // G = Q^H P, exactly Hermitian
+  gram(h, Q, ldq, P, n, n, k, k, h->G, k, true, st);
+  if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[0], st));
+  const int sweeps = small_eig(h, k, h->opts.eig_solver, st);
+  if (stats && sweeps >= 0) {
+    stats->eig_jacobi_calls++;
+    stats->eig_jacobi_sweeps += sweeps;
+  }
   if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[1], st));
   // Ritz vectors Z = Q W
   gemm_nn(h, n, k, k, Q, ldq, h->G, k, Zb, n, st);
@@ -975,7 +1013,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     qr_step(h, h->V, n, ne, 0, h->W, &stats, st);
     debug_check("QR", 0, true);
     rr_step(h, H, ldh, h->V, n, ne, norm_est, h->W, h->Z, &stats.t_rr, &stats.t_resid, st,
-            mixed ? h->Rres : nullptr, n, &stats.t_rr_eig);
+            mixed ? h->Rres : nullptr, n, &stats.t_rr_eig, &stats);
     debug_check("Rayleigh-Ritz", 0, false);
     have_ritz = true;
     if (after_rr(-1, ne, 0)) stats.iterations = 0;
@@ -1018,7 +1056,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
     Range r_rr("rayleigh_ritz_residual");
     rr_step(h, H, ldh, off(h->V, (int64_t)L * n, h->esz), n, ka, norm_est, h->W, h->Z, &stats.t_rr,
             &stats.t_resid, st, mixed ? off(h->Rres, (int64_t)L * n, h->esz) : nullptr, n,
-            &stats.t_rr_eig);
+            &stats.t_rr_eig, &stats);
     r_rr.end();
     debug_check("Rayleigh-Ritz", L, false);
     if (after_rr(it, ka, n64)) break;
@@ -1236,6 +1274,7 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
       h->Rres = dev_alloc(h, (size_t)n * ne * h->esz);
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
+    h->jac_ws = dev_alloc(h, jacobi_ws_bytes(h->cplx, (int)ne));
     if (o.adjoint_reserve > 0) {
       h->adj = dev_alloc(h, 2 * (size_t)n * ne * h->esz);
       ensure_tape(h, (int)ne, o.adjoint_reserve);
@@ -1454,6 +1493,28 @@ chase_status chase_rayleigh_ritz(chase_handle_t h, const void* H, int64_t ldh, v
     CHASE_HIP(hipMemcpyAsync(ritz, h->d_evals, k * 8, hipMemcpyDeviceToHost, st));
     if (resid) CHASE_HIP(hipMemcpyAsync(resid, h->d_res, k * 8, hipMemcpyDeviceToHost, st));
     CHASE_HIP(hipStreamSynchronize(st));
+  });
+}
+
+chase_status chase_heev(chase_handle_t h, void* G, int64_t ldg, int k, int method, double* evals,
+                        int* sweeps, void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(G && evals, "NULL pointer argument");
+    CHASE_REQUIRE(k >= 1 && k <= h->ne, "k must be in [1, nev+nex]");
+    CHASE_REQUIRE(ldg >= k, "leading dimension smaller than k");
+    CHASE_REQUIRE(method == CHASE_EIG_AUTO || method == CHASE_EIG_LIBRARY ||
+                      method == CHASE_EIG_JACOBI,
+                  "unknown eigensolver");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    copy_cols(h->cplx, G, ldg, h->G, k, k, k, st);
+    const int sw = small_eig(h, k, method, st);
+    if (sw < 0) check_info(h, st, "Hermitian eigensolver");
+    copy_cols(h->cplx, h->G, k, G, ldg, k, k, st);
+    CHASE_HIP(hipMemcpyAsync(evals, h->d_evals, k * 8, hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
+    if (sweeps) *sweeps = sw < 0 ? 0 : sw;
   });
 }
 

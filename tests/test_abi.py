@@ -40,7 +40,7 @@ def test_default_opts():
     o = pk.default_opts()
     assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
             o.max_iter, o.filter_prec, o.initial_rr, o.fp64_tail) == (36, 2, 1, 25, 4, 50, 0, 0, -1)
-    assert (o.seed, o.debug, o.adjoint_reserve) == (0, 0, 0)
+    assert (o.seed, o.debug, o.adjoint_reserve, o.eig_solver) == (0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("struct", ["chase_opts", "chase_stats"])
