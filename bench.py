@@ -40,6 +40,9 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
 # for its two-term form (the block as bf16: hi*hi, lo*hi)
 EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0, "bf16x2": 2.0}
 PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
+# dense eigensolver of the Rayleigh-Ritz step (chase_opts.eig_solver)
+EIG_CODE = {"auto": 0, "library": 1, "jacobi": 2}
+EIG_CHOICE = "auto"
 KERNEL_NAME = {
     "fp64": "gemm_kernel<double,double,complex,N,N,CHEB,8,Gauss,128x64> (FP64 MFMA 16x16x4)",
     "fp32": "gemm_kernel<float,float,complex,N,N,CHEB,16,Gauss,128x64> (FP32 MFMA 16x16x4)",
@@ -423,7 +426,8 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
     norm = max(abs(lam[0]), abs(lam[-1]))
     results = {}
     for prec in precs:
-        opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if verbose else 0)
+        opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if verbose else 0,
+                               eig_solver=EIG_CODE[EIG_CHOICE])
         if max_deg is not None:
             opts.max_deg = max_deg
         handle = pk.Handle(n, nev, nex, H.dtype, opts)
@@ -476,6 +480,7 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
             phases={k: st[k] for k in ("t_lanczos", "t_filter", "t_qr", "t_rr", "t_rr_eig",
                                        "t_resid")},
             qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
+            eig_jacobi_calls=st["eig_jacobi_calls"], eig_jacobi_sweeps=st["eig_jacobi_sweeps"],
             stats=st, evals=ev)
         if warm_start:
             results[prec]["warm_start"] = warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm,
@@ -488,7 +493,7 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
 
 MODE_KEYS = ("solve_s", "converged", "max_resid", "max_eig_err_rel", "max_resid_independent",
              "iterations", "matvecs_fp64", "matvecs_low", "fp64_tail", "filter_tflops", "phases",
-             "qr_shifted", "qr_householder")
+             "qr_shifted", "qr_householder", "eig_jacobi_calls", "eig_jacobi_sweeps")
 
 
 def mode_summary(m, prec, fp64_solve_s):
@@ -631,6 +636,10 @@ def main():
                     help="also time a sequence step: H + E (||E||_2 = 1e-5 ||H||_2, seeded "
                          "Hermitian) solved cold and warm-started from the previous "
                          "eigenvectors, in each timed filter mode")
+    ap.add_argument("--eig-solver", default="auto", choices=sorted(EIG_CODE),
+                    help="dense eigensolver of the Rayleigh-Ritz step: auto (the library's "
+                         "Jacobi once the projected matrix is near diagonal, else rocSOLVER), "
+                         "library (rocSOLVER) or jacobi")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--max-deg", type=int, default=None,
                     help="cap of the optimised filter degree (library default 36)")
@@ -642,6 +651,8 @@ def main():
                     help="only run a plain 1 GiB device copy (calibrates the HBM byte "
                          "counters of rocprofv3 --pmc)")
     args = ap.parse_args()
+    global EIG_CHOICE
+    EIG_CHOICE = args.eig_solver
     if args.library_reference:
         print(json.dumps(library_gemm_reference()), flush=True)
         return
@@ -744,6 +755,8 @@ def main():
         "max_resid_independent": r["max_resid_independent"],
         "max_eig_err_rel": r["max_eig_err_rel"], "phases_s": r["phases"],
         "qr_shifted_passes": r["qr_shifted"], "qr_householder": r["qr_householder"],
+        "eig_solver": EIG_CHOICE, "eig_jacobi_calls": r["eig_jacobi_calls"],
+        "eig_jacobi_sweeps": r["eig_jacobi_sweeps"],
         "roofline": roof,
         # memory-bound step: the Lanczos block GEMV (H read once per launch,
         # 4 vectors), HIP events around each launch of the timed solves

@@ -25,7 +25,7 @@ constexpr int JB = 16;       // indices per block
 constexpr int JM = 2 * JB;   // order of a pair's subproblem
 constexpr int JLD = JM + 1;  // LDS leading dimension (padded against bank conflicts)
 constexpr int JT = 256;      // threads per workgroup
-constexpr int JCG = JT / JM; // column groups of the tile products (8)
+constexpr int JCG = JT / JM; // column groups of the tile stores (8)
 constexpr int NPART = 256;   // workgroups of the norm reduction
 
 struct cd {
@@ -68,28 +68,29 @@ __host__ __device__ inline int rr_player(int m, int r, int j) {
 
 // Rotation that zeroes the (a, b) entry of the 2 x 2 Hermitian
 // [[app, apq], [conj(apq), aqq]]: with apq = g ph (g = |apq|, |ph| = 1),
-// u = [[cs, sn], [-sn conj(ph), cs conj(ph)]] and u^H A u is diagonal; t =
-// sn / cs is the smaller root of t^2 + 2 tau t - 1 = 0, tau = (aqq - app) /
-// (2 g).  Entries with g <= thr are left alone (identity).
+// u = [[cs, sn], [-sn conj(ph), cs conj(ph)]] = diag(1, conj(ph)) R, R the
+// real rotation [[cs, sn], [-sn, cs]], and u^H A u is diagonal.  t = sn / cs
+// is the root of smaller magnitude of t^2 + 2 tau t - 1 = 0, tau = (aqq -
+// app) / (2 g), written as t = sign(d) 2 g / (|d| + sqrt(d^2 + 4 g^2)),
+// d = aqq - app (one square root and one division on the dependent path).
+// Entries with g <= thr are left alone (identity).
 template <class T>
 __device__ __forceinline__ int jac_rotation(double app, double aqq, T apq, double thr, double& cs,
                                             double& sn, T& ph) {
-  const double g = sqrt(abs2(apq));
-  if (!(g > thr)) {
+  const double g2 = abs2(apq);
+  if (!(g2 > thr * thr)) {
     cs = 1.0;
     sn = 0.0;
     ph = from_real<T>(1.0);
     return 0;
   }
-  const double tau = (aqq - app) / (2.0 * g);
-  double t;
-  if (fabs(tau) > 1e150)
-    t = 0.5 / tau;
-  else
-    t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  cs = 1.0 / sqrt(1.0 + t * t);
+  const double d = aqq - app;
+  const double rg = rsqrt(g2);
+  const double r = sqrt(fma(d, d, 4.0 * g2));
+  const double t = copysign(2.0 * g2 * rg, d) / (fabs(d) + r);
+  cs = rsqrt(fma(t, t, 1.0));
   sn = t * cs;
-  ph = apq * (1.0 / g);
+  ph = apq * rg;
   return 1;
 }
 
@@ -142,12 +143,16 @@ __device__ void pair_body(const T* __restrict__ G, int64_t ldg, int k, int nb, i
       const int ai = ra[i], bi = rb[i], aj = ra[j], bj = rb[j];
       const double ci = rcs[i], si = rsn[i], cj = rcs[j], sj = rsn[j];
       const T pi_ = rph[i], pjc = conj_(rph[j]);
-      const T m00 = S[aj * JLD + ai], m01 = S[bj * JLD + ai];
-      const T m10 = S[aj * JLD + bi], m11 = S[bj * JLD + bi];
-      const T r00 = m00 * cj - m01 * (pjc * sj), r01 = m00 * sj + m01 * (pjc * cj);
-      const T r10 = m10 * cj - m11 * (pjc * sj), r11 = m10 * sj + m11 * (pjc * cj);
-      T n00 = r00 * ci - r10 * (pi_ * si), n01 = r01 * ci - r11 * (pi_ * si);
-      T n10 = r00 * si + r10 * (pi_ * ci), n11 = r01 * si + r11 * (pi_ * ci);
+      // u_i^H M u_j = R_i^T (D_i^H M D_j) R_j: phases first, then the real
+      // rotations
+      const T m00 = S[aj * JLD + ai];
+      const T m01 = S[bj * JLD + ai] * pjc;
+      const T m10 = pi_ * S[aj * JLD + bi];
+      const T m11 = S[bj * JLD + bi] * (pi_ * pjc);
+      const T r00 = m00 * cj - m01 * sj, r01 = m00 * sj + m01 * cj;
+      const T r10 = m10 * cj - m11 * sj, r11 = m10 * sj + m11 * cj;
+      T n00 = r00 * ci - r10 * si, n01 = r01 * ci - r11 * si;
+      T n10 = r00 * si + r10 * ci, n11 = r01 * si + r11 * ci;
       if (i == j) {
         // the pivot block: exactly diagonal and real after its rotation
         n00 = from_real<T>(real_(n00));
@@ -167,11 +172,40 @@ __device__ void pair_body(const T* __restrict__ G, int64_t ldg, int k, int nb, i
       const int rho = e % JM, j = e / JM;
       const int aj = ra[j], bj = rb[j];
       const double cj = rcs[j], sj = rsn[j];
-      const T pjc = conj_(rph[j]);
-      const T u0 = U[aj * JLD + rho], u1 = U[bj * JLD + rho];
-      U[aj * JLD + rho] = u0 * cj - u1 * (pjc * sj);
-      U[bj * JLD + rho] = u0 * sj + u1 * (pjc * cj);
+      const T u0 = U[aj * JLD + rho], u1 = U[bj * JLD + rho] * conj_(rph[j]);
+      U[aj * JLD + rho] = u0 * cj - u1 * sj;
+      U[bj * JLD + rho] = u0 * sj + u1 * cj;
     }
+    __syncthreads();
+  }
+  // One Newton-Schulz step towards the nearest unitary, U <- U (3 I - U^H U) / 2:
+  // the rounding of the rotations leaves U unitary only to a few ulps per
+  // inner round, and applying a non-unitary J^H G J shifts the eigenvalues by
+  // that much in every round; the step brings it back to rounding level.
+  // M = U^H U goes into S (no longer needed).
+  const int i = tid % JM, cg = tid / JM;
+  if (any) {
+#pragma unroll
+    for (int m = 0; m < JM / JCG; ++m) {
+      const int c = cg + JCG * m;
+      T acc = from_real<T>(0.0);
+#pragma unroll 4
+      for (int l = 0; l < JM; ++l) mac(acc, conj_(U[i * JLD + l]), U[c * JLD + l]);
+      S[c * JLD + i] = acc;
+    }
+    __syncthreads();
+    T nu[JM / JCG];
+#pragma unroll
+    for (int m = 0; m < JM / JCG; ++m) {
+      const int c = cg + JCG * m;
+      T acc = from_real<T>(0.0);
+#pragma unroll 4
+      for (int l = 0; l < JM; ++l) mac(acc, U[l * JLD + i], S[c * JLD + l]);
+      nu[m] = U[c * JLD + i] * 1.5 - acc * 0.5;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < JM / JCG; ++m) U[(cg + JCG * m) * JLD + i] = nu[m];
     __syncthreads();
   }
   T* Uo = ubuf + (int64_t)pair * JM * JM;
@@ -179,19 +213,48 @@ __device__ void pair_body(const T* __restrict__ G, int64_t ldg, int k, int nb, i
   if (tid == 0) flags[pair] = any;
 }
 
-// acc[m] (output (i, cg + JCG m) of a JM x JM tile) = sum_l A(i, l) B(l, cg + JCG m)
-// for A(i, l) at As[l * JLD + i] and B(l, c) at Bs[c * JLD + l] (LDS).
-template <class T>
-__device__ __forceinline__ void tile_product(const T* As, const T* Bs, int i, int cg,
-                                             T (&acc)[JM / JCG]) {
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+// Y = A B for JM x JM tiles in LDS on the FP64 matrix cores (16x16x4 MFMA),
+// A(i, l) at As[l * JLD + i] and B(l, c) at Bs[l * JLD + c].  Wave w of the
+// four computes the quadrant of rows 16 (w & 1) and columns 16 (w >> 1).
+// The operands go in swapped (B first), so the instruction produces the
+// quadrant transposed: lane L holds Y(16 (w & 1) + L % 16, 16 (w >> 1) +
+// L / 16 + 4 r) in out[r] (rows run along the lanes, as stores want them).
+__device__ __forceinline__ void tile_mma(const double* As, const double* Bs, double (&out)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 16 * (w & 1), c0 = 16 * (w >> 1), l16 = lane & 15, lk = lane >> 4;
+  d4v acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int m = 0; m < JM / JCG; ++m) acc[m] = from_real<T>(0.0);
-#pragma unroll 4
-  for (int l = 0; l < JM; ++l) {
-    const T x = As[l * JLD + i];
-#pragma unroll
-    for (int m = 0; m < JM / JCG; ++m) mac(acc[m], x, Bs[(cg + JCG * m) * JLD + l]);
+  for (int k0 = 0; k0 < JM; k0 += 4) {
+    const double a = As[(k0 + lk) * JLD + i0 + l16];
+    const double b = Bs[(k0 + lk) * JLD + c0 + l16];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, acc, 0, 0, 0);
   }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = acc[r];
+}
+__device__ __forceinline__ void tile_mma(const cd* As, const cd* Bs, cd (&out)[4]) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int i0 = 16 * (w & 1), c0 = 16 * (w >> 1), l16 = lane & 15, lk = lane >> 4;
+  d4v re = {0.0, 0.0, 0.0, 0.0}, im = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k0 = 0; k0 < JM; k0 += 4) {
+    const cd a = As[(k0 + lk) * JLD + i0 + l16];
+    const cd b = Bs[(k0 + lk) * JLD + c0 + l16];
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(b.x, a.x, re, 0, 0, 0);
+    re = __builtin_amdgcn_mfma_f64_16x16x4f64(-b.y, a.y, re, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(b.y, a.x, im, 0, 0, 0);
+    im = __builtin_amdgcn_mfma_f64_16x16x4f64(b.x, a.y, im, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = cd{re[r], im[r]};
+}
+
+// Position of out[r] of tile_mma in this thread: row, column.
+__device__ __forceinline__ int mma_row() { return 16 * ((threadIdx.x >> 6) & 1) + (threadIdx.x & 15); }
+__device__ __forceinline__ int mma_col(int r) {
+  return 16 * (threadIdx.x >> 7) + ((threadIdx.x & 63) >> 4) + 4 * r;
 }
 
 // JM rows of V (row chunk `chunk`) times the columns of pair b of round
@@ -202,7 +265,6 @@ __device__ void vtile_body(T* __restrict__ V, int64_t ldv, int k, int nb, int ro
                            T* Xs, T* Bs) {
   if (!flags[b]) return;
   const int tid = threadIdx.x;
-  const int i = tid % JM, cg = tid / JM;
   const int b0 = rr_player(nb, round, b), b1 = rr_player(nb, round, nb - 1 - b);
   auto gb = [&](int l) { return l < JB ? b0 * JB + l : b1 * JB + (l - JB); };
   const T* Ub = ubuf + (int64_t)b * JM * JM;
@@ -213,15 +275,16 @@ __device__ void vtile_body(T* __restrict__ V, int64_t ldv, int k, int nb, int ro
     T v = from_real<T>(0.0);
     if (r0 + r < k && gc < k) v = V[r0 + r + (int64_t)gc * ldv];
     Xs[c * JLD + r] = v;
-    Bs[c * JLD + r] = Ub[e];
+    Bs[r * JLD + c] = Ub[e];
   }
   __syncthreads();
-  T acc[JM / JCG];
-  tile_product(Xs, Bs, i, cg, acc);
+  T out[4];
+  tile_mma(Xs, Bs, out);
+  const int64_t row = r0 + mma_row();
 #pragma unroll
-  for (int m = 0; m < JM / JCG; ++m) {
-    const int gc = gb(cg + JCG * m);
-    if (r0 + i < k && gc < k) V[r0 + i + (int64_t)gc * ldv] = acc[m];
+  for (int r = 0; r < 4; ++r) {
+    const int gc = gb(mma_col(r));
+    if (row < k && gc < k) V[row + (int64_t)gc * ldv] = out[r];
   }
 }
 
@@ -257,8 +320,8 @@ __global__ __launch_bounds__(JT) void jac_stage2_k(T* __restrict__ G, int64_t ld
                                                    int round, const T* __restrict__ ubuf,
                                                    const int* __restrict__ flags) {
   __shared__ T Xs[JM * JLD];  // X(i, l) at Xs[l * JLD + i]; later the result Y
-  __shared__ T Bs[JM * JLD];  // U_b (B(l, c) at Bs[c * JLD + l]), then A = U_a^H
-  __shared__ T Ts[JM * JLD];  // X U_b, T(l, c) at Ts[c * JLD + l]
+  __shared__ T Bs[JM * JLD];  // U_b (B(l, c) at Bs[l * JLD + c]), then A = U_a^H
+  __shared__ T Ts[JM * JLD];  // X U_b, T(l, c) at Ts[l * JLD + c]
   const int tid = threadIdx.x;
   const int i = tid % JM, cg = tid / JM;
   const int t = blockIdx.x;
@@ -280,13 +343,13 @@ __global__ __launch_bounds__(JT) void jac_stage2_k(T* __restrict__ G, int64_t ld
     T v = from_real<T>(0.0);
     if (gr < k && gc < k) v = G[gr + (int64_t)gc * ldg];
     Xs[c * JLD + r] = v;
-    Bs[c * JLD + r] = fb ? Ub[e] : from_real<T>(r == c ? 1.0 : 0.0);
+    Bs[r * JLD + c] = fb ? Ub[e] : from_real<T>(r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  T acc[JM / JCG];
-  tile_product(Xs, Bs, i, cg, acc);
+  T out[4];
+  tile_mma(Xs, Bs, out);  // T = X U_b, stored as T(l, c) at Ts[l * JLD + c]
 #pragma unroll
-  for (int m = 0; m < JM / JCG; ++m) Ts[(cg + JCG * m) * JLD + i] = acc[m];
+  for (int r = 0; r < 4; ++r) Ts[mma_row() * JLD + mma_col(r)] = out[r];
   __syncthreads();
   // A(c, r) = conj(U_a(r, c)) at Bs[r * JLD + c]
   for (int e = tid; e < JM * JM; e += JT) {
@@ -294,9 +357,9 @@ __global__ __launch_bounds__(JT) void jac_stage2_k(T* __restrict__ G, int64_t ld
     Bs[r * JLD + c] = fa ? conj_(Ua[e]) : from_real<T>(r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  tile_product(Bs, Ts, i, cg, acc);
+  tile_mma(Bs, Ts, out);  // Y = U_a^H T, stored as Y(i, c) at Xs[c * JLD + i]
 #pragma unroll
-  for (int m = 0; m < JM / JCG; ++m) Xs[(cg + JCG * m) * JLD + i] = acc[m];
+  for (int r = 0; r < 4; ++r) Xs[mma_col(r) * JLD + mma_row()] = out[r];
   __syncthreads();
   if (a == b) {
     const int gi = ga(i);

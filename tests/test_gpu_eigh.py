@@ -66,7 +66,7 @@ def test_jacobi_and_library_agree(pk, cplx):
     ev_l, W_l, sw_l = pk.chase_heev(to_gpu(G), method=pk.EIG_LIBRARY)
     assert sw >= 1 and sw_l == 0
     scale = np.max(np.abs(ev_l))
-    assert np.max(np.abs(ev_j - ev_l)) <= 1e-12 * scale
+    assert np.max(np.abs(ev_j - ev_l)) <= 20 * k * 2.0 ** -53 * scale
     _check_decomposition(G, ev_l, to_np(W_l))
 
 
@@ -154,8 +154,15 @@ def test_jacobi_at_full_block_size(pk, k):
     ev, W, sweeps = pk.chase_heev(Gd, method=pk.EIG_JACOBI, handle=h)
     ev_l, _, _ = pk.chase_heev(Gd, method=pk.EIG_LIBRARY, handle=h)
     assert 1 <= sweeps <= 8
-    scale = np.max(np.abs(ev_l))
-    assert np.max(np.abs(ev - ev_l)) <= 1e-12 * scale
+    # both solvers are backward stable: each eigenvalue within a small
+    # multiple of k u ||G||_2 of the host LAPACK's (a Jacobi whose rotation
+    # products drift from unitary shifts the eigenvalues by ~1e-12 here)
+    ref = np.linalg.eigvalsh(G)
+    scale = np.max(np.abs(ref))
+    bound = 2 * k * 2.0 ** -53 * scale
+    err_j, err_l = np.max(np.abs(ev - ref)), np.max(np.abs(ev_l - ref))
+    print(f"k={k}: Jacobi {err_j / scale:.2e}, library {err_l / scale:.2e} (relative)")
+    assert err_j <= bound and err_l <= bound, (err_j / scale, err_l / scale)
     evd = torch.from_numpy(ev).to(W.device).to(W.dtype)
     res = torch.max(torch.abs(Gd @ W - W * evd[None, :])).item()
     orth = torch.max(torch.abs(W.mH @ W - torch.eye(k, dtype=W.dtype, device=W.device))).item()
