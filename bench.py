@@ -506,6 +506,48 @@ def mode_summary(m, prec, fp64_solve_s):
     return out
 
 
+def eigensolver_block(pk, k, reps=2):
+    """The Rayleigh-Ritz step's dense eigensolve on its own (chase_heev):
+    the library's Jacobi against rocSOLVER's divide and conquer on seeded
+    complex Hermitian k x k matrices, dense (a random projected matrix, as in
+    the first iteration) and diag(lambda) + E with ||E||_F = 1e-1, 1e-2, 1e-4
+    of ||lambda|| (the later iterations).  Mean of `reps` timed calls after
+    one untimed call; eigenvalue difference relative to max |lambda|."""
+    import torch
+
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3)
+    a = torch.randn((k, k), dtype=torch.complex128, device="cuda", generator=g)
+    dense = (a + a.mH) / 2
+    lam = torch.sort(torch.rand(k, dtype=torch.float64, device="cuda", generator=g) * 2 - 1).values
+    e = dense / torch.linalg.norm(dense) * torch.linalg.norm(lam)
+    cases = {"dense": dense}
+    for off in (1e-1, 1e-2, 1e-4):
+        cases[f"near_diagonal_{off:g}"] = torch.diag(lam).to(e.dtype) + off * e
+    h = pk.Handle(k, k - 1, 1, torch.complex128)
+    out = {"k": k, "dtype": "c128", "cases": {}}
+    for name, G in cases.items():
+        G = G.contiguous()
+        row = {}
+        for meth, code in (("jacobi", pk.EIG_JACOBI), ("library", pk.EIG_LIBRARY)):
+            pk.chase_heev(G, method=code, handle=h)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                ev, W, sw = pk.chase_heev(G, method=code, handle=h)
+            torch.cuda.synchronize()
+            row[meth + "_ms"] = (time.perf_counter() - t0) / reps * 1e3
+            row[meth + "_evals"] = ev
+            if meth == "jacobi":
+                row["jacobi_sweeps"] = sw
+        row["eig_diff_rel"] = float(abs(row.pop("jacobi_evals") - row["library_evals"]).max()
+                                    / abs(row.pop("library_evals")).max())
+        out["cases"][name] = row
+        log(f"eigensolver k={k} {name}: {row}")
+    h.close()
+    return out
+
+
 def library_gemm_reference():
     """Rates of the vendor's own GEMMs on this GPU (torch -> hipBLASLt /
     rocBLAS), timed the same way as the library's kernels, as the practical
@@ -640,6 +682,9 @@ def main():
                     help="dense eigensolver of the Rayleigh-Ritz step: auto (the library's "
                          "Jacobi once the projected matrix is near diagonal, else rocSOLVER), "
                          "library (rocSOLVER) or jacobi")
+    ap.add_argument("--eigensolver", type=int, default=None, metavar="K",
+                    help="only time the Rayleigh-Ritz eigensolve (Jacobi and rocSOLVER) "
+                         "on K x K complex Hermitian matrices")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--max-deg", type=int, default=None,
                     help="cap of the optimised filter degree (library default 36)")
@@ -655,6 +700,10 @@ def main():
     EIG_CHOICE = args.eig_solver
     if args.library_reference:
         print(json.dumps(library_gemm_reference()), flush=True)
+        return
+    if args.eigensolver is not None:
+        import paper_2205_02491_amd as pk
+        print(json.dumps(eigensolver_block(pk, args.eigensolver)), flush=True)
         return
     if args.calib_copy:
         import torch
