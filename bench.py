@@ -33,13 +33,23 @@ sys.path.insert(0, ROOT)
 METRIC = "solve s @resid≤1e-10 & filter TFLOP/s (% MFMA peak), FP64 vs mixed"
 # dense MFMA peaks of one MI355X (TFLOP/s) for the arithmetic each filter
 # mode executes: FP64, FP32, BF16 (split-BF16 runs on the BF16 matrix cores)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x2": 2500.0,
+               # FP64-accurate products on the INT8 matrix cores: the algorithmic
+               # rate is set against the FP64 peak it replaces
+               "fp64i8": 78.6, "bf16x2i8": 2500.0}
+# FP64 filter products on the INT8 matrix cores (chase_opts.fp64_emulation):
+# the moduli of each mode, the INT8 operations per algorithmic FLOP
+# (complex: three real products per modulus, 2 n^2 k each, against 8 n^2 k)
+# and the dense INT8 peak
+EMU_MODULI = {"fp64i8": 14, "bf16x2i8": 14}
+INT8_PEAK_TOPS = 5000.0
 # executed MFMA FLOPs per algorithmic FLOP (8 per complex multiply-add):
 # three real products per complex product (Gauss) for FP64/FP32, twelve BF16
 # products (four real products x hi*hi, hi*lo, lo*hi) for split-BF16, eight
 # for its two-term form (the block as bf16: hi*hi, lo*hi)
-EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0, "bf16x2": 2.0}
-PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3}
+EXEC_PER_ALGO = {"fp64": 0.75, "fp32": 0.75, "bf16x3": 3.0, "bf16x2": 2.0,
+                 "fp64i8": 3 * 14 * 2 / 8.0, "bf16x2i8": 2.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x2": 3, "fp64i8": 0, "bf16x2i8": 3}
 # dense eigensolver of the Rayleigh-Ritz step (chase_opts.eig_solver)
 EIG_CODE = {"auto": 0, "library": 1, "jacobi": 2}
 EIG_CHOICE = "auto"
@@ -49,6 +59,10 @@ KERNEL_NAME = {
     "bf16x3": "gemm_bf16x3_kernel<complex, 3 terms> (BF16 MFMA 32x32x16, 256x128 tiles)",
     "bf16x2": "gemm_bf16x3_kernel<complex, 2 terms; start pass 3 terms> (BF16 MFMA 32x32x16, "
               "256x128 tiles)",
+    "fp64i8": "FP64 step on INT8: 42 rocBLAS INT8 GEMMs (14 moduli x 3 Gauss products) + "
+              "crt_cheb_k (Garner reconstruction, Chebyshev epilogue); executed = INT8 ops",
+    "bf16x2i8": "gemm_bf16x3_kernel<complex, 2 terms; start pass 3 terms> (BF16 MFMA 32x32x16); "
+                "FP64 steps and Rayleigh-Ritz H Q on INT8 (14 moduli)",
 }
 
 # HBM bytes per filter launch from rocprofv3 PMC runs (FETCH_SIZE x 2.0 and
@@ -85,7 +99,7 @@ def exec_per_algo(prec, st, deg, ne):
     of its own precision.  The two-term split-BF16 mode runs the start block's
     low-precision steps with three terms (deg - fp64_tail steps over all ne
     columns) and the defect-form passes with two."""
-    if prec != "bf16x2" or st["matvecs_low"] == 0:
+    if prec not in ("bf16x2", "bf16x2i8") or st["matvecs_low"] == 0:
         return EXEC_PER_ALGO[prec]
     d0 = deg + (deg & 1)
     start = min(st["matvecs_low"], (d0 - st["fp64_tail"]) * ne)
@@ -427,7 +441,8 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
     results = {}
     for prec in precs:
         opts = pk.default_opts(filter_prec=PREC_CODE[prec], verbose=1 if verbose else 0,
-                               eig_solver=EIG_CODE[EIG_CHOICE])
+                               eig_solver=EIG_CODE[EIG_CHOICE],
+                               fp64_emulation=EMU_MODULI.get(prec, 0))
         if max_deg is not None:
             opts.max_deg = max_deg
         handle = pk.Handle(n, nev, nex, H.dtype, opts)
@@ -455,7 +470,7 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
         # the filter launches of this mode's precision (a mixed solve also
         # runs FP64 filter steps: the start block's FP64 tail, FP64 ranks)
         per_mv = (8.0 if H.is_complex() else 2.0) * n * n
-        if prec == "fp64":
+        if prec in ("fp64", "fp64i8"):
             fl = sum(s["filter_flops"] for s in stats)
             kt = sum(s["t_filter_kernels"] for s in stats)
             launches = sum(s["filter_launches"] for s in stats)
@@ -500,6 +515,14 @@ def mode_summary(m, prec, fp64_solve_s):
     out = {k: m[k] for k in MODE_KEYS}
     out["filter_frac_peak"] = m["filter_tflops"] / PEAK_TFLOPS[prec]
     out["filter_executed_frac"] = m["exec_per_algo"] * m["filter_tflops"] / PEAK_TFLOPS[prec]
+    if prec == "fp64i8":
+        # FP64-accurate products on INT8: the algorithmic rate against the
+        # FP64 peak (above 1 when faster than the FP64 matrix cores can be),
+        # the executed INT8 operations against the INT8 peak
+        out["filter_executed_frac"] = m["exec_per_algo"] * m["filter_tflops"] / INT8_PEAK_TOPS
+        out["filter_executed_unit"] = "INT8 TOPS / %g" % INT8_PEAK_TOPS
+    if prec in EMU_MODULI:
+        out["fp64_emulation_moduli"] = EMU_MODULI[prec]
     out["avg_launch_ms"] = m["avg_launch_ms"]
     if fp64_solve_s is not None and prec != "fp64":
         out["speedup_vs_fp64"] = fp64_solve_s / m["solve_s"]
@@ -661,8 +684,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="geometric20k", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="all",
-                    choices=["fp64", "fp32", "bf16x3", "bf16x2", "both", "all"],
-                    help="filter modes to time: both = fp64 + fp32, all = fp64 + fp32 + bf16x3")
+                    choices=["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8", "both",
+                             "all"],
+                    help="filter modes to time: both = fp64 + fp32, all = every mode; fp64i8 "
+                         "and bf16x2i8 run the FP64 products on the INT8 matrix cores "
+                         "(14 moduli)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed-workload", action="store_true",
                     help="skip the n=30000 FP64-versus-mixed block of the default workload")
@@ -670,6 +696,9 @@ def main():
                     help="skip the vendor GEMM rates printed beside the roofline")
     ap.add_argument("--library-reference", action="store_true",
                     help="only time the vendor GEMMs (torch -> hipBLASLt / rocBLAS)")
+    ap.add_argument("--mixed-extra", nargs="*", default=[], choices=["fp64i8"],
+                    help="further modes for the n=30000 block (fp64i8: every FP64 product "
+                         "on INT8, about 40 s more)")
     ap.add_argument("--mixed-steps", type=int, default=1,
                     help="timed solves per mode in the n=30000 block")
     ap.add_argument("--mixed-warmup", type=int, default=0,
@@ -760,8 +789,9 @@ def main():
     torch.cuda.empty_cache()
     log(f"generated {args.workload} n={n} in {time.perf_counter() - t0:.1f} s")
 
-    precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"]}.get(args.prec,
-                                                                          [args.prec])
+    precs = {"both": ["fp64", "fp32"],
+             "all": ["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8"]}.get(args.prec,
+                                                                                 [args.prec])
     results = time_modes(pk, prob, wl, precs, args.steps, args.warmup, args.workload,
                          verbose=args.verbose, max_deg=args.max_deg, warm_start=args.warm_start)
     H = prob["H"]
@@ -791,7 +821,8 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["solve_s"] * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": {"fp64": "c128", "fp32": "c64/c128", "bf16x3": "bf16x3/c128",
-                  "bf16x2": "bf16x2/c128"}[main_prec],
+                  "bf16x2": "bf16x2/c128", "fp64i8": "int8-crt/c128",
+                  "bf16x2i8": "bf16x2/int8-crt/c128"}[main_prec],
         "data": "synthetic planted-spectrum Hermitian (seeded, generated on the GPU)",
         "config": {"workload": f"{args.workload}", "n": n, "nev": nev, "nex": nex,
                    "degree": wl["deg"], "tol": wl["tol"], "filter": main_prec,
@@ -816,7 +847,8 @@ def main():
                          "avg_launch_ms": r["lanczos_gemv_ms"],
                          "bytes_per_launch": n * n * (16 if H.is_complex() else 8)},
     }
-    for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3"), ("bf16x2", "mixed_bf16x2")):
+    for low, key in (("fp32", "mixed"), ("bf16x3", "mixed_bf16x3"), ("bf16x2", "mixed_bf16x2"),
+                     ("fp64i8", "fp64_on_int8"), ("bf16x2i8", "mixed_bf16x2_int8")):
         if low not in results or main_prec == low:
             continue
         out[key] = mode_summary(results[low], low, r["solve_s"])
@@ -841,7 +873,8 @@ def main():
         # the metric's FP64-versus-mixed comparison on the workload where the
         # mixed-precision policy does its work (many iterations, defect form)
         out["mixed_workload"] = mixed_workload_block(
-            pk, ["fp64", "fp32", "bf16x3", "bf16x2"], args.mixed_steps, args.mixed_warmup)
+            pk, ["fp64", "fp32", "bf16x3", "bf16x2", "bf16x2i8"] + args.mixed_extra,
+            args.mixed_steps, args.mixed_warmup)
     print(json.dumps(out), flush=True)
 
 

@@ -134,7 +134,20 @@ typedef struct chase_opts {
                           iterations of a solve) and the divide-and-conquer
                           solver of the ROCm library otherwise;
                           CHASE_EIG_LIBRARY / CHASE_EIG_JACOBI force one    */
-  int reserved[1];
+  int fp64_emulation;  /* 0 (default): FP64 filter products on the FP64 matrix
+                          cores.  8, 10, 12, 14 or 16: every FP64 filter
+                          product (the FP64 mode's, the FP64 tail and FP64
+                          ranks of the mixed modes) runs on the INT8 matrix
+                          cores as an exact integer product modulo that many
+                          moduli <= 256, recovered by Chinese remaindering
+                          (Ozaki scheme II): rows of H and columns of the
+                          block are rounded to integers of about
+                          (log2 M - log2 n) / 2 bits, M the moduli's product
+                          (14 moduli at n = 20000: 46-47 bits, the accuracy
+                          class of FP64 products).  H must be Hermitian and
+                          n <= 65535; the handle keeps 3N n^2 bytes of
+                          residues of H (complex; N n^2 real) and 15N n
+                          (nev+nex) bytes of per-step buffers               */
 } chase_opts;
 
 /* Dense Hermitian eigensolvers for the Rayleigh-Ritz step (chase_opts

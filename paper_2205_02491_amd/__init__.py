@@ -49,7 +49,7 @@ class Opts(ctypes.Structure):
                 ("verbose", ctypes.c_int), ("initial_rr", ctypes.c_int),
                 ("fp64_tail", ctypes.c_int), ("seed", ctypes.c_int),
                 ("debug", ctypes.c_int), ("adjoint_reserve", ctypes.c_int),
-                ("eig_solver", ctypes.c_int), ("reserved", ctypes.c_int * 1)]
+                ("eig_solver", ctypes.c_int), ("fp64_emulation", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

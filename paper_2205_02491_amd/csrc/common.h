@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <cstdint>
 #include <stdexcept>
@@ -213,6 +214,29 @@ void cg_dir(bool cplx, void* P, const void* R, int64_t ld, int64_t n, int64_t k,
 // (0 on the diagonal and between equal eigenvalues), k x k
 void sym_divdiff(bool cplx, const void* M, int64_t ldm, const double* lam, int64_t k, void* E,
                  int64_t lde, hipStream_t st);
+
+// ------------------------------------------------------------------ FP64 products on INT8
+// Integer modular emulation of the FP64 filter product (crt.hip).
+constexpr int kCrtMaxModuli = 16;
+struct CrtBasis {
+  int n_mod;               // number of moduli (8, 10, 12, 14 or 16)
+  int m[kCrtMaxModuli];    // the moduli
+  int inv[kCrtMaxModuli];  // (m_0 ... m_{t-1})^{-1} mod m_t
+  int pa, pb;              // bits of the integer forms of H's rows and X's columns
+};
+// Basis for products with inner dimension K.
+CrtBasis crt_basis(int n_mod, int64_t K, bool cplx);
+// Device bytes: residue planes of H (+ row exponents); per-step planes of a
+// block of up to kmax columns, their INT32 products and column exponents.
+size_t crt_h_bytes(bool cplx, int64_t n, int n_mod);
+size_t crt_x_bytes(bool cplx, int64_t n, int kmax, int n_mod);
+// Residue planes of the Hermitian H into hbuf (crt_h_bytes).
+void crt_prepare_h(bool cplx, const void* H, int64_t ldh, int64_t n, const CrtBasis& B,
+                   void* hbuf, hipStream_t st);
+// One filter step with the EPI_CHEB epilogue (GemmArgs as for gemm(); A must
+// be the H whose planes hbuf holds), products on the INT8 matrix cores.
+void crt_cheb(bool cplx, const GemmArgs& g, const CrtBasis& B, const void* hbuf, void* xbuf,
+              int kmax, rocblas_handle rb, hipStream_t st);
 
 // ------------------------------------------------------------------ Jacobi eigensolver
 // Device workspace of the block Jacobi eigensolver for orders up to kmax.

@@ -60,6 +60,11 @@ struct chase_handle_s {
   size_t tape_bytes = 0;
   void* adj = nullptr;  // eigenvector adjoint: two n x ne blocks (first use; in allocs)
   void* jac_ws = nullptr;  // Jacobi eigensolver workspace (orders up to ne)
+  // FP64 filter products on the INT8 matrix cores (opts.fp64_emulation > 0):
+  // residue planes of H and the per-step buffers
+  void* crt_h = nullptr;
+  void* crt_x = nullptr;
+  CrtBasis crt{};
   std::vector<int> tape_deg;
   std::vector<Coef> tape_coef;
   int tape_k = 0;
@@ -163,7 +168,7 @@ size_t splitk_ws_elems(int ne) {
 constexpr int kMaxDegree = 1000;  // largest filter degree any entry point accepts
 
 struct Sizes {
-  size_t blocks, small, lz, ws, h32, adj, total;
+  size_t blocks, small, lz, ws, h32, adj, crt, total;
   int lz_splits;
 };
 
@@ -189,7 +194,9 @@ Sizes sizes(chase_dtype dt, int64_t n, int nev, int nex, const chase_opts& o) {
   // and a filter tape of adjoint_reserve steps over ne columns
   if (o.adjoint_reserve > 0)
     s.adj = 2 * (size_t)n * ne * esz + (size_t)(o.adjoint_reserve + 1) * n * ne * esz;
-  s.total = s.blocks + s.ws + s.small + s.lz + s.h32 + s.adj;
+  if (o.fp64_emulation > 0)
+    s.crt = crt_h_bytes(cplx, n, o.fp64_emulation) + crt_x_bytes(cplx, n, (int)ne, o.fp64_emulation);
+  s.total = s.blocks + s.ws + s.small + s.lz + s.h32 + s.adj + s.crt;
   return s;
 }
 
@@ -203,6 +210,9 @@ void validate_opts(const chase_opts& o) {
   CHASE_REQUIRE(o.max_iter >= 1, "max_iter < 1");
   CHASE_REQUIRE(o.initial_rr == 0 || o.initial_rr == 1, "initial_rr must be 0 or 1");
   CHASE_REQUIRE(o.fp64_tail >= -1 && o.fp64_tail <= kMaxDegree, "fp64_tail out of range [-1,1000]");
+  CHASE_REQUIRE(o.fp64_emulation == 0 || o.fp64_emulation == 8 || o.fp64_emulation == 10 ||
+                    o.fp64_emulation == 12 || o.fp64_emulation == 14 || o.fp64_emulation == 16,
+                "fp64_emulation must be 0, 8, 10, 12, 14 or 16");
   CHASE_REQUIRE(o.eig_solver == CHASE_EIG_AUTO || o.eig_solver == CHASE_EIG_LIBRARY ||
                     o.eig_solver == CHASE_EIG_JACOBI,
                 "unknown eig_solver");
@@ -320,6 +330,20 @@ void split_h(chase_handle_s* h, const void* H, int64_t ldh, hipStream_t st) {
   split_s8(h->cplx, true, H, ldh, h->n, h->n, s8_pad(h->n, S8_COLS_A), h->Hs8, h->s8_groups, st);
 }
 
+// One FP64 filter step (EPI_CHEB): on the FP64 matrix cores, or with the
+// handle's fp64_emulation on the INT8 ones (H's residue planes must have been
+// prepared from the same H, crt_prepare_h).
+void fp64_step(chase_handle_s* h, const GemmArgs& g, hipStream_t st) {
+  if (h->crt_h)
+    crt_cheb(h->cplx, g, h->crt, h->crt_h, h->crt_x, h->ne, h->rb, st);
+  else
+    gemm(h->cplx, PREC_F64, OP_N, OP_N, EPI_CHEB, g, st);
+}
+
+void prepare_h_products(chase_handle_s* h, const void* H, int64_t ldh, hipStream_t st) {
+  if (h->crt_h) crt_prepare_h(h->cplx, H, ldh, h->n, h->crt, h->crt_h, st);
+}
+
 // X (n x k, ld ldx) <- p_{m_a}(H) x_a ; Wb (n x k, ld ldw) ping-pong scratch.
 // degrees non-decreasing, even, >= 2.  With a low precision `prec`, steps
 // s >= fp64_from run with FP64 products instead (timed into *ft64): the
@@ -376,7 +400,10 @@ void run_filter(chase_handle_s* h, const void* H, int64_t ldh, void* X, int64_t 
       bsteps->prepare(g, cols, (s < mmax && a1 < k && s + 1 < fp64_from) ? a1 - a0 : -1, st);
     }
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
-    gemm(h->cplx, low ? prec : PREC_F64, OP_N, OP_N, EPI_CHEB, g, st);
+    if (low && prec != PREC_F64)
+      gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
+    else
+      fp64_step(h, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
     if (bsteps && low) bsteps->advance(g);
     FilterTiming& fs = low ? ft : *ft64;
@@ -472,7 +499,10 @@ void run_filter_defect(chase_handle_s* h, const void* H, int64_t ldh, void* V, i
       bsteps->prepare(g, cols, (s < mmax && a1 < k) ? a1 - a0 : -1, st);
     }
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1)], st));
-    gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
+    if (prec == PREC_F64)
+      fp64_step(h, g, st);
+    else
+      gemm(h->cplx, prec, OP_N, OP_N, EPI_CHEB, g, st);
     CHASE_HIP(hipEventRecord(h->evs[2 * (s - 1) + 1], st));
     if (bsteps) bsteps->advance(g);
     ft.matvecs += cols;
@@ -671,8 +701,16 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
   const int64_t n = h->n;
   const bool cplx = h->cplx;
   auto t0 = clk::now();
-  // P = H Q   (the HEMM of the Rayleigh-Ritz step)
-  gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
+  // P = H Q   (the HEMM of the Rayleigh-Ritz step; with fp64_emulation on
+  // the INT8 matrix cores, as the filter's FP64 products)
+  if (h->crt_h) {
+    GemmArgs g = gargs(n, k, n, H, ldh, Q, ldq, P, n);
+    g.gamma = 0.0;
+    g.beta = 0.0;
+    fp64_step(h, g, st);
+  } else {
+    gemm_nn(h, n, k, n, H, ldh, Q, ldq, P, n, st);
+  }
   // G = Q^H P, exactly Hermitian
   gram(h, Q, ldq, P, n, n, k, k, h->G, k, true, st);
   if (t_eig) CHASE_HIP(hipEventRecord(h->eig_ev[0], st));
@@ -883,6 +921,7 @@ void solve_impl(chase_handle_s* h, const void* H, int64_t ldh, double tol, int d
   stats.fp64_tail = fp64_tail;
   if (plow == PREC_F32 && mixed && h->H32) to_f32(cplx, H, ldh, h->H32, n, st);
   if (is_split_bf16(plow)) split_h(h, H, ldh, st);
+  prepare_h_products(h, H, ldh, st);
 
   if (V0)
     CHASE_HIP(hipMemcpyAsync(h->V, V0, (size_t)n * ne * h->esz, hipMemcpyDeviceToDevice, st));
@@ -1275,6 +1314,12 @@ chase_status chase_create(chase_handle_t* out, chase_dtype dtype, int64_t n, int
     }
     h->d_coef = static_cast<double*>(dev_alloc(h, (size_t)(kMaxDegree + 1) * ne * 8));
     h->jac_ws = dev_alloc(h, jacobi_ws_bytes(h->cplx, (int)ne));
+    if (o.fp64_emulation > 0) {
+      CHASE_REQUIRE(n <= 65535, "fp64_emulation needs n <= 65535");
+      h->crt = crt_basis(o.fp64_emulation, n, h->cplx);
+      h->crt_h = dev_alloc(h, crt_h_bytes(h->cplx, n, o.fp64_emulation));
+      h->crt_x = dev_alloc(h, crt_x_bytes(h->cplx, n, (int)ne, o.fp64_emulation));
+    }
     if (o.adjoint_reserve > 0) {
       h->adj = dev_alloc(h, 2 * (size_t)n * ne * h->esz);
       ensure_tape(h, (int)ne, o.adjoint_reserve);
@@ -1417,6 +1462,7 @@ chase_status chase_filter(chase_handle_t h, const void* H, int64_t ldh, void* X,
     if (record_tape) ensure_tape(h, k, degrees[k - 1]);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
     if (prec == CHASE_PREC_BF16X3 || prec == CHASE_PREC_BF16X2) split_h(h, H, ldh, st);
+    prepare_h_products(h, H, ldh, st);
     FilterTiming ft;
     h->tape_valid = false;
     run_filter(h, H, ldh, X, ldx, h->W, h->n, k, degrees, b_sup, mu_1, mu_ne, to_prec(prec),
@@ -1453,6 +1499,7 @@ chase_status chase_filter_ritz(chase_handle_t h, const void* H, int64_t ldh, voi
     set_stream(h, st);
     if (prec == CHASE_PREC_FP32 && h->H32) to_f32(h->cplx, H, ldh, h->H32, h->n, st);
     if (prec == CHASE_PREC_BF16X3 || prec == CHASE_PREC_BF16X2) split_h(h, H, ldh, st);
+    prepare_h_products(h, H, ldh, st);
     FilterTiming ft;
     run_filter_defect(h, H, ldh, V, ldv, R, ldr, h->W, h->Z, k, degrees, theta, b_sup, mu_1,
                       mu_ne, to_prec(prec), ft, st);
@@ -1488,6 +1535,7 @@ chase_status chase_rayleigh_ritz(chase_handle_t h, const void* H, int64_t ldh, v
     CHASE_REQUIRE(norm_scale > 0, "norm_scale must be positive");
     hipStream_t st = static_cast<hipStream_t>(stream);
     set_stream(h, st);
+    prepare_h_products(h, H, ldh, st);
     rr_step(h, H, ldh, Q, ldq, k, norm_scale, h->W, h->Z, nullptr, nullptr, st);
     check_info(h, st, "Hermitian eigensolver");
     CHASE_HIP(hipMemcpyAsync(ritz, h->d_evals, k * 8, hipMemcpyDeviceToHost, st));

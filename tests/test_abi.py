@@ -40,7 +40,7 @@ def test_default_opts():
     o = pk.default_opts()
     assert (o.max_deg, o.deg_extra, o.optimize_degree, o.lanczos_steps, o.lanczos_vecs,
             o.max_iter, o.filter_prec, o.initial_rr, o.fp64_tail) == (36, 2, 1, 25, 4, 50, 0, 0, -1)
-    assert (o.seed, o.debug, o.adjoint_reserve, o.eig_solver) == (0, 0, 0, 0)
+    assert (o.seed, o.debug, o.adjoint_reserve, o.eig_solver, o.fp64_emulation) == (0, 0, 0, 0, 0)
 
 
 @pytest.mark.parametrize("struct", ["chase_opts", "chase_stats"])
@@ -107,6 +107,17 @@ def test_workspace_bytes_matches_one_gpu_memory_estimate():
         res = pk.chase_workspace_bytes(n, 200, 60, cplx=cplx,
                                        opts=pk.default_opts(adjoint_reserve=20))
         assert res - base == (2 + 21) * n * ne * esz
+    # FP64 products on INT8: residue planes of H (three per modulus for
+    # complex: Re, Im, Re + Im; one real) and row exponents, per-step planes
+    # of the block with their INT32 products and column exponents
+    for cplx, planes in ((True, 3), (False, 1)):
+        n, ne, nm = 20000, 1300, 14
+        base = pk.chase_workspace_bytes(n, 1000, 300, cplx=cplx)
+        emu = pk.chase_workspace_bytes(n, 1000, 300, cplx=cplx,
+                                       opts=pk.default_opts(fp64_emulation=nm))
+        a256 = lambda b: -(-b // 256) * 256
+        assert emu - base == (a256(planes * nm * n * n) + 4 * n + a256(planes * nm * n * ne)
+                              + a256(4 * planes * nm * n * ne) + 4 * ne + 256)
     assert pk.chase_workspace_bytes(10, 8, 4) == 0      # nev + nex > n
     assert pk.chase_workspace_bytes(10, 0, 4) == 0
 
@@ -133,6 +144,13 @@ def test_create_rejects_bad_sizes_without_gpu():
         o = pk.default_opts(fp64_tail=bad)
         st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
         assert st == pk.ERR_ARG and b"fp64_tail" in L.chase_last_error()
+    for bad in (-1, 4, 9, 18):
+        o = pk.default_opts(fp64_emulation=bad)
+        st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
+        assert st == pk.ERR_ARG and b"fp64_emulation" in L.chase_last_error()
+    o = pk.default_opts(eig_solver=3)
+    st = L.chase_create(ctypes.byref(h), 0, 100, 2, 2, ctypes.byref(o))
+    assert st == pk.ERR_ARG and b"eig_solver" in L.chase_last_error()
     assert L.chase_eigvec_adjoint(None, None, 0, None, 0, 1, None, None, 0, None, 0, 1e-10, 10,
                                   None, None) == pk.ERR_ARG
     assert b"handle" in L.chase_last_error()
