@@ -58,22 +58,26 @@ def _sin_angle(Va, Vb):
     return float(torch.linalg.eigvalsh(P.mH @ P).max().clamp(min=0).sqrt())
 
 
-@pytest.mark.parametrize("prec", ["fp64", "bf16x2", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "bf16x2", "fp32", "bf16x2i8", "fp64i8"])
 def test_solve_cluster30k(problem, prec):
+    """fp64i8 / bf16x2i8: the FP64 products (the filter's FP64 steps and
+    Rayleigh-Ritz's H Q) on the INT8 matrix cores, 14 moduli."""
     import torch
     pk, prob = problem
     announce(f"full-size solve cluster121 n={N} prec={prec}")
-    code = {"fp64": pk.PREC_FP64, "fp32": pk.PREC_FP32, "bf16x2": pk.PREC_BF16X2}[prec]
+    code = {"fp64": pk.PREC_FP64, "fp32": pk.PREC_FP32, "bf16x2": pk.PREC_BF16X2,
+            "bf16x2i8": pk.PREC_BF16X2, "fp64i8": pk.PREC_FP64}[prec]
     H = prob["H"]
-    ev, vec, res, st = pk.chase_solve(H, NEV, NEX, TOL, DEG, prob["V0"], prob["S"],
-                                      opts=pk.default_opts(filter_prec=code))
+    ev, vec, res, st = pk.chase_solve(
+        H, NEV, NEX, TOL, DEG, prob["V0"], prob["S"],
+        opts=pk.default_opts(filter_prec=code, fp64_emulation=14 if prec.endswith("i8") else 0))
     announce(f"  {prec}: {st['t_all']:.1f} s, {st['iterations']} it, "
              f"matvecs fp64 {st['matvecs_fp64']} low {st['matvecs_low']}")
     assert st["converged"]
     # the multi-iteration path: locking over several iterations, degree
     # re-optimisation, and in the mixed modes the defect-form passes
     assert st["iterations"] >= 2
-    if prec != "fp64":
+    if prec not in ("fp64", "fp64i8"):
         assert st["matvecs_low"] > 0
         assert st["matvecs_low"] > st["matvecs_fp64"]
     lam = prob["lam"]
