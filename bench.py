@@ -94,11 +94,13 @@ PAPER_TABLE2_GPU = {
 }
 
 
-def exec_per_algo(prec, st, deg, ne):
+def exec_per_algo(prec, st, deg, ne, cplx=True):
     """Executed MFMA FLOPs per algorithmic FLOP over a solve's filter launches
     of its own precision.  The two-term split-BF16 mode runs the start block's
     low-precision steps with three terms (deg - fp64_tail steps over all ne
     columns) and the defect-form passes with two."""
+    if prec == "fp64i8" and not cplx:
+        return float(EMU_MODULI[prec])  # one real product per modulus, 2 n^2 k each
     if prec not in ("bf16x2", "bf16x2i8") or st["matvecs_low"] == 0:
         return EXEC_PER_ALGO[prec]
     d0 = deg + (deg & 1)
@@ -488,7 +490,7 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
             max_resid_independent=indep,
             iterations=st["iterations"], matvecs_fp64=st["matvecs_fp64"],
             matvecs_low=st["matvecs_low"], fp64_tail=st["fp64_tail"],
-            exec_per_algo=exec_per_algo(prec, st, wl["deg"], nev + nex),
+            exec_per_algo=exec_per_algo(prec, st, wl["deg"], nev + nex, H.is_complex()),
             filter_tflops=fl / kt / 1e12, filter_kernel_s=kt / steps,
             filter_launches=launches // steps,
             avg_launch_ms=kt / launches * 1e3, flops_per_launch=fl / launches,
@@ -685,7 +687,7 @@ def main():
     ap.add_argument("--workload", default="geometric20k", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="all",
                     choices=["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8", "both",
-                             "all"],
+                             "all", "int8"],
                     help="filter modes to time: both = fp64 + fp32, all = every mode; fp64i8 "
                          "and bf16x2i8 run the FP64 products on the INT8 matrix cores "
                          "(14 moduli)")
@@ -761,8 +763,8 @@ def main():
         print(json.dumps(bench_diff(args, wl)), flush=True)
         return
     if args.workload == "table2":
-        precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"]}.get(
-            args.prec, [args.prec])
+        precs = {"both": ["fp64", "fp32"], "all": ["fp64", "fp32", "bf16x3", "bf16x2"],
+                 "int8": ["fp64", "fp64i8", "bf16x2", "bf16x2i8"]}.get(args.prec, [args.prec])
         if "fp64" not in precs:
             precs = ["fp64"] + precs
         t2 = table2_block(pk, precs, args.steps, args.warmup)
@@ -790,8 +792,8 @@ def main():
     log(f"generated {args.workload} n={n} in {time.perf_counter() - t0:.1f} s")
 
     precs = {"both": ["fp64", "fp32"],
-             "all": ["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8"]}.get(args.prec,
-                                                                                 [args.prec])
+             "all": ["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8"],
+             "int8": ["fp64", "fp64i8", "bf16x2", "bf16x2i8"]}.get(args.prec, [args.prec])
     results = time_modes(pk, prob, wl, precs, args.steps, args.warmup, args.workload,
                          verbose=args.verbose, max_deg=args.max_deg, warm_start=args.warm_start)
     H = prob["H"]
