@@ -161,23 +161,130 @@ __global__ __launch_bounds__(TPB) void crt_xplanes_k(const double* __restrict__ 
   }
 }
 
+// Four consecutive entries per thread (n a multiple of 4): the residues of
+// each plane go out as one packed 32-bit store (byte e = entry e).
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void crt_hplanes4_k(const double* __restrict__ H, int64_t ldh,
+                                                      int64_t n, const int* __restrict__ sigma,
+                                                      CrtBasis B, int8_t* __restrict__ planes) {
+  const int64_t i = blockIdx.y;
+  const int64_t j0 = 4 * ((int64_t)blockIdx.x * TPB + threadIdx.x);
+  if (j0 >= n) return;
+  const int s = sigma[i];
+  const int64_t o = i * n + j0;
+  const int64_t plane = n * n;
+  if constexpr (CPLX) {
+    double re[4], im[4], sm[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      re[e] = rint(ldexp(H[2 * (j0 + e + i * ldh)], s));
+      im[e] = rint(ldexp(-H[2 * (j0 + e + i * ldh) + 1], s));
+      sm[e] = re[e] + im[e];
+    }
+    for (int t = 0; t < B.n_mod; ++t) {
+      const int m = B.m[t];
+      const double minv = 1.0 / (double)m;
+      uint32_t wr = 0, wi = 0, ws = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        wr |= (uint32_t)(uint8_t)bres(re[e], m, minv) << (8 * e);
+        wi |= (uint32_t)(uint8_t)bres(im[e], m, minv) << (8 * e);
+        ws |= (uint32_t)(uint8_t)bres(sm[e], m, minv) << (8 * e);
+      }
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 0) * plane + o) = wr;
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 1) * plane + o) = wi;
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 2) * plane + o) = ws;
+    }
+  } else {
+    double v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = rint(ldexp(H[j0 + e + i * ldh], s));
+    for (int t = 0; t < B.n_mod; ++t) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w |= (uint32_t)(uint8_t)bres(v[e], B.m[t], 1.0 / (double)B.m[t]) << (8 * e);
+      *reinterpret_cast<uint32_t*>(planes + t * plane + o) = w;
+    }
+  }
+}
+
+template <bool CPLX>
+__global__ __launch_bounds__(TPB) void crt_xplanes4_k(const double* __restrict__ X, int64_t ldx,
+                                                      int64_t n, int cols,
+                                                      const int* __restrict__ tau, CrtBasis B,
+                                                      int8_t* __restrict__ planes) {
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * TPB + threadIdx.x);
+  if (i0 >= n) return;
+  const int s = tau[j];
+  const int64_t o = j * n + i0;
+  const int64_t plane = n * (int64_t)cols;
+  if constexpr (CPLX) {
+    double re[4], im[4], sm[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      re[e] = rint(ldexp(X[2 * (i0 + e + j * ldx)], s));
+      im[e] = rint(ldexp(X[2 * (i0 + e + j * ldx) + 1], s));
+      sm[e] = re[e] + im[e];
+    }
+    for (int t = 0; t < B.n_mod; ++t) {
+      const int m = B.m[t];
+      const double minv = 1.0 / (double)m;
+      uint32_t wr = 0, wi = 0, ws = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        wr |= (uint32_t)(uint8_t)bres(re[e], m, minv) << (8 * e);
+        wi |= (uint32_t)(uint8_t)bres(im[e], m, minv) << (8 * e);
+        ws |= (uint32_t)(uint8_t)bres(sm[e], m, minv) << (8 * e);
+      }
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 0) * plane + o) = wr;
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 1) * plane + o) = wi;
+      *reinterpret_cast<uint32_t*>(planes + (3 * t + 2) * plane + o) = ws;
+    }
+  } else {
+    double v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = rint(ldexp(X[i0 + e + j * ldx], s));
+    for (int t = 0; t < B.n_mod; ++t) {
+      uint32_t w = 0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w |= (uint32_t)(uint8_t)bres(v[e], B.m[t], 1.0 / (double)B.m[t]) << (8 * e);
+      *reinterpret_cast<uint32_t*>(planes + t * plane + o) = w;
+    }
+  }
+}
+
 // Garner: the integer x with x = r_t (mod m_t), |x| < M / 2, from residues
 // r_t in [0, m_t): balanced mixed-radix digits v_t, x = v_0 + m_0 (v_1 + m_1
 // (v_2 + ...)), evaluated in FP64 from the top digit (error <= ~NM u |x|).
-// The moduli are compile-time constants (the reductions become multiplies).
+// The moduli are compile-time constants.
+// x mod m in [0, m) for an integer-valued float |x| < 2^24 (exact: the
+// quotient estimate is off by at most one, which the two corrections undo)
+__device__ __forceinline__ float fmod_m(float x, float m, float minv) {
+  const float q = floorf(x * minv);
+  float r = fmaf(-q, m, x);
+  if (r < 0.f) r += m;
+  if (r >= m) r -= m;
+  return r;
+}
+
 template <int NM>
 __device__ __forceinline__ double garner(const int (&r)[NM], const CrtBasis& B) {
-  int v[NM];
+  // every intermediate is an integer below 2^17 in magnitude, exact in FP32,
+  // whose multiply-adds run at full rate (32-bit integer multiplies do not)
+  float v[NM];
 #pragma unroll
   for (int t = 0; t < NM; ++t) {
-    const int m = kModuli[t];
-    // (v_0 + m_0 (v_1 + ... + m_{t-2} v_{t-1})) mod m_t, in (-m_t, m_t)
-    int acc = 0;
+    const float m = (float)kModuli[t], minv = 1.0f / (float)kModuli[t];
+    // (v_0 + m_0 (v_1 + ... + m_{t-2} v_{t-1})) mod m_t
+    float acc = 0.f;
 #pragma unroll
-    for (int s = t - 1; s >= 0; --s) acc = (acc * kModuli[s] + v[s]) % m;
-    int d = ((r[t] - acc) % m + m) % m;
-    d = (d * B.inv[t]) % m;
-    if (d > (m - 1) / 2) d -= m;
+    for (int s = t - 1; s >= 0; --s) acc = fmod_m(fmaf(acc, (float)kModuli[s], v[s]), m, minv);
+    float d = fmod_m((float)r[t] - acc, m, minv);
+    d = fmod_m(d * (float)B.inv[t], m, minv);
+    if (d > (m - 1.f) * 0.5f) d -= m;
     v[t] = d;
   }
   double x = 0.0;
@@ -242,12 +349,108 @@ __global__ __launch_bounds__(TPB) void crt_cheb_k(const int32_t* __restrict__ P,
   }
 }
 
+// The epilogue of one entry: out = alpha (c - gamma Xs) + beta out [+ cj F].
+template <bool CPLX>
+__device__ __forceinline__ void cheb_store(const GemmArgs& g, int64_t i, int64_t j, double vr,
+                                           double vi) {
+  const double* Xs = static_cast<const double*>(g.B);
+  double* Cd = static_cast<double*>(g.C);
+  const int64_t oc = i + j * g.ldc;
+  if constexpr (CPLX) {
+    vr = g.alpha * (vr - g.gamma * Xs[2 * (i + j * g.ldb)]);
+    vi = g.alpha * (vi - g.gamma * Xs[2 * (i + j * g.ldb) + 1]);
+    if (g.beta != 0.0) {
+      vr += g.beta * Cd[2 * oc];
+      vi += g.beta * Cd[2 * oc + 1];
+    }
+    if (g.colcoef) {
+      const double cj = g.colcoef[j];
+      const double* Fd = static_cast<const double*>(g.F);
+      vr += cj * Fd[2 * (i + j * g.ldf)];
+      vi += cj * Fd[2 * (i + j * g.ldf) + 1];
+    }
+    Cd[2 * oc] = vr;
+    Cd[2 * oc + 1] = vi;
+  } else {
+    double v = g.alpha * (vr - g.gamma * Xs[i + j * g.ldb]);
+    if (g.beta != 0.0) v += g.beta * Cd[oc];
+    if (g.colcoef) v += g.colcoef[j] * static_cast<const double*>(g.F)[i + j * g.ldf];
+    Cd[oc] = v;
+  }
+}
+
+// Four consecutive rows per thread (n a multiple of 4): 16-byte loads of the
+// INT32 products; the residues of the four entries are kept packed (one
+// byte each) until each entry's reconstruction.
+template <bool CPLX, int NM>
+__global__ __launch_bounds__(TPB) void crt_cheb4_k(const int32_t* __restrict__ P, int64_t n,
+                                                   int cols, CrtBasis B,
+                                                   const int* __restrict__ sigma,
+                                                   const int* __restrict__ tau, GemmArgs g) {
+  typedef int i4v __attribute__((ext_vector_type(4)));
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = 4 * ((int64_t)blockIdx.x * TPB + threadIdx.x);
+  if (i0 >= n) return;
+  const int64_t plane = n * (int64_t)cols;
+  const int64_t o = j * n + i0;
+  uint32_t pr[NM], pi[NM];
+#pragma unroll
+  for (int t = 0; t < NM; ++t) {
+    const int m = kModuli[t];
+    const double minv = 1.0 / (double)m;
+    uint32_t wr = 0, wi = 0;
+    if constexpr (CPLX) {
+      const i4v a = *reinterpret_cast<const i4v*>(P + (3 * t + 0) * plane + o);
+      const i4v b = *reinterpret_cast<const i4v*>(P + (3 * t + 1) * plane + o);
+      const i4v c = *reinterpret_cast<const i4v*>(P + (3 * t + 2) * plane + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int p1 = ures32(a[e], m, minv), p2 = ures32(b[e], m, minv);
+        const int p3 = ures32(c[e], m, minv);
+        wr |= (uint32_t)((p1 - p2 + m) % m) << (8 * e);
+        wi |= (uint32_t)((p3 - p1 - p2 + 2 * m) % m) << (8 * e);
+      }
+    } else {
+      const i4v a = *reinterpret_cast<const i4v*>(P + t * plane + o);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) wr |= (uint32_t)ures32(a[e], m, minv) << (8 * e);
+    }
+    pr[t] = wr;
+    pi[t] = wi;
+  }
+  const int ej = tau[j];
+  // one entry at a time (the reconstructions of four entries side by side
+  // would hold four sets of digits)
+#pragma unroll 1
+  for (int e = 0; e < 4; ++e) {
+    const int64_t i = i0 + e;
+    const int sc = -(sigma[i] + ej);
+    int r[NM];
+#pragma unroll
+    for (int t = 0; t < NM; ++t) r[t] = (int)((pr[t] >> (8 * e)) & 0xffu);
+    const double vr = ldexp(garner<NM>(r, B), sc);
+    double vi = 0.0;
+    if constexpr (CPLX) {
+#pragma unroll
+      for (int t = 0; t < NM; ++t) r[t] = (int)((pi[t] >> (8 * e)) & 0xffu);
+      vi = ldexp(garner<NM>(r, B), sc);
+    }
+    cheb_store<CPLX>(g, i, j, vr, vi);
+  }
+}
+
 template <bool CPLX, int NM>
 void launch_cheb(const int32_t* prod, int64_t n, int cols, const CrtBasis& B, const int* sigma,
                  const int* tau, const GemmArgs& g, hipStream_t st) {
-  const dim3 grid((unsigned)((n + TPB - 1) / TPB), (unsigned)cols);
-  hipLaunchKernelGGL((crt_cheb_k<CPLX, NM>), grid, dim3(TPB), 0, st, prod, n, cols, B, sigma, tau,
-                     g);
+  if (n % 4 == 0) {
+    const dim3 grid((unsigned)((n / 4 + TPB - 1) / TPB), (unsigned)cols);
+    hipLaunchKernelGGL((crt_cheb4_k<CPLX, NM>), grid, dim3(TPB), 0, st, prod, n, cols, B, sigma,
+                       tau, g);
+  } else {
+    const dim3 grid((unsigned)((n + TPB - 1) / TPB), (unsigned)cols);
+    hipLaunchKernelGGL((crt_cheb_k<CPLX, NM>), grid, dim3(TPB), 0, st, prod, n, cols, B, sigma,
+                       tau, g);
+  }
 }
 
 template <bool CPLX>
@@ -333,16 +536,26 @@ void crt_prepare_h(bool cplx, const void* H, int64_t ldh, int64_t n, const CrtBa
   int8_t* planes = static_cast<int8_t*>(hbuf);
   int* sigma = reinterpret_cast<int*>(planes + h_planes_bytes(cplx, n, B.n_mod));
   const double* Hd = static_cast<const double*>(H);
+  const bool v4 = n % 4 == 0;
+  const dim3 grid((unsigned)(((v4 ? n / 4 : n) + TPB - 1) / TPB), (unsigned)n);
   if (cplx) {
     hipLaunchKernelGGL(crt_rowexp_k<true>, dim3((unsigned)n), dim3(TPB), 0, st, Hd, ldh, n, B.pa,
                        sigma);
-    hipLaunchKernelGGL(crt_hplanes_k<true>, dim3((unsigned)((n + TPB - 1) / TPB), (unsigned)n),
-                       dim3(TPB), 0, st, Hd, ldh, n, static_cast<const int*>(sigma), B, planes);
+    if (v4)
+      hipLaunchKernelGGL(crt_hplanes4_k<true>, grid, dim3(TPB), 0, st, Hd, ldh, n,
+                         static_cast<const int*>(sigma), B, planes);
+    else
+      hipLaunchKernelGGL(crt_hplanes_k<true>, grid, dim3(TPB), 0, st, Hd, ldh, n,
+                         static_cast<const int*>(sigma), B, planes);
   } else {
     hipLaunchKernelGGL(crt_rowexp_k<false>, dim3((unsigned)n), dim3(TPB), 0, st, Hd, ldh, n, B.pa,
                        sigma);
-    hipLaunchKernelGGL(crt_hplanes_k<false>, dim3((unsigned)((n + TPB - 1) / TPB), (unsigned)n),
-                       dim3(TPB), 0, st, Hd, ldh, n, static_cast<const int*>(sigma), B, planes);
+    if (v4)
+      hipLaunchKernelGGL(crt_hplanes4_k<false>, grid, dim3(TPB), 0, st, Hd, ldh, n,
+                         static_cast<const int*>(sigma), B, planes);
+    else
+      hipLaunchKernelGGL(crt_hplanes_k<false>, grid, dim3(TPB), 0, st, Hd, ldh, n,
+                         static_cast<const int*>(sigma), B, planes);
   }
   CHASE_HIP(hipGetLastError());
 }
@@ -361,15 +574,24 @@ void crt_cheb(bool cplx, const GemmArgs& g, const CrtBasis& B, const void* hbuf,
   int* tau = reinterpret_cast<int*>(reinterpret_cast<char*>(prod) +
                                     x_prod_bytes(cplx, n, kmax, B.n_mod));
   const double* Xs = static_cast<const double*>(g.B);
-  const dim3 grid((unsigned)((n + TPB - 1) / TPB), (unsigned)cols);
+  const bool v4 = n % 4 == 0;
+  const dim3 grid((unsigned)(((v4 ? n / 4 : n) + TPB - 1) / TPB), (unsigned)cols);
   if (cplx) {
     hipLaunchKernelGGL(crt_colexp_k<true>, dim3(cols), dim3(TPB), 0, st, Xs, g.ldb, n, B.pb, tau);
-    hipLaunchKernelGGL(crt_xplanes_k<true>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
-                       static_cast<const int*>(tau), B, xplanes);
+    if (v4)
+      hipLaunchKernelGGL(crt_xplanes4_k<true>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
+                         static_cast<const int*>(tau), B, xplanes);
+    else
+      hipLaunchKernelGGL(crt_xplanes_k<true>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
+                         static_cast<const int*>(tau), B, xplanes);
   } else {
     hipLaunchKernelGGL(crt_colexp_k<false>, dim3(cols), dim3(TPB), 0, st, Xs, g.ldb, n, B.pb, tau);
-    hipLaunchKernelGGL(crt_xplanes_k<false>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
-                       static_cast<const int*>(tau), B, xplanes);
+    if (v4)
+      hipLaunchKernelGGL(crt_xplanes4_k<false>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
+                         static_cast<const int*>(tau), B, xplanes);
+    else
+      hipLaunchKernelGGL(crt_xplanes_k<false>, grid, dim3(TPB), 0, st, Xs, g.ldb, n, cols,
+                         static_cast<const int*>(tau), B, xplanes);
   }
   CHASE_HIP(hipGetLastError());
   // P exact integer products, one per (modulus, Gauss term): H planes are
