@@ -713,6 +713,8 @@ def main():
                     help="dense eigensolver of the Rayleigh-Ritz step: auto (the library's "
                          "Jacobi once the projected matrix is near diagonal, else rocSOLVER), "
                          "library (rocSOLVER) or jacobi")
+    ap.add_argument("--moduli", type=int, default=None, choices=[8, 10, 12, 14, 16],
+                    help="moduli of the INT8 FP64-product modes (default 14)")
     ap.add_argument("--eigensolver", type=int, default=None, metavar="K",
                     help="only time the Rayleigh-Ritz eigensolve (Jacobi and rocSOLVER) "
                          "on K x K complex Hermitian matrices")
@@ -729,6 +731,10 @@ def main():
     args = ap.parse_args()
     global EIG_CHOICE
     EIG_CHOICE = args.eig_solver
+    if args.moduli is not None:
+        for key in EMU_MODULI:
+            EMU_MODULI[key] = args.moduli
+        EXEC_PER_ALGO["fp64i8"] = 3 * args.moduli * 2 / 8.0
     if args.library_reference:
         print(json.dumps(library_gemm_reference()), flush=True)
         return

@@ -144,10 +144,14 @@ typedef struct chase_opts {
                           block are rounded to integers of about
                           (log2 M - log2 n) / 2 bits, M the moduli's product
                           (14 moduli at n = 20000: 46-47 bits, the accuracy
-                          class of FP64 products).  H must be Hermitian and
-                          n <= 65535; the handle keeps 3N n^2 bytes of
-                          residues of H (complex; N n^2 real) and 15N n
-                          (nev+nex) bytes of per-step buffers               */
+                          class of FP64 products).  Rayleigh-Ritz's H Q,
+                          from which the reported residuals come, runs on
+                          INT8 only with 14 or 16 moduli (with 12 the
+                          residuals were off by half of tol = 1e-10); fewer
+                          moduli serve the filter alone.  H must be
+                          Hermitian and n <= 65535; the handle keeps 3N n^2
+                          bytes of residues of H (complex; N n^2 real) and
+                          15N n (nev+nex) bytes of per-step buffers         */
 } chase_opts;
 
 /* Dense Hermitian eigensolvers for the Rayleigh-Ritz step (chase_opts

@@ -218,6 +218,8 @@ void sym_divdiff(bool cplx, const void* M, int64_t ldm, const double* lam, int64
 // ------------------------------------------------------------------ FP64 products on INT8
 // Integer modular emulation of the FP64 filter product (crt.hip).
 constexpr int kCrtMaxModuli = 16;
+// fewest moduli with which Rayleigh-Ritz's H Q also runs on INT8
+constexpr int kCrtMinModuliRR = 14;
 struct CrtBasis {
   int n_mod;               // number of moduli (8, 10, 12, 14 or 16)
   int m[kCrtMaxModuli];    // the moduli

@@ -702,8 +702,11 @@ void rr_step(chase_handle_s* h, const void* H, int64_t ldh, void* Q, int64_t ldq
   const bool cplx = h->cplx;
   auto t0 = clk::now();
   // P = H Q   (the HEMM of the Rayleigh-Ritz step; with fp64_emulation on
-  // the INT8 matrix cores, as the filter's FP64 products)
-  if (h->crt_h) {
+  // the INT8 matrix cores, as the filter's FP64 products, if the moduli keep
+  // the FP64 accuracy class: the residuals the solve reports come from P,
+  // and with 12 moduli (integer forms of ~39 bits at n = 20000) they were
+  // off by half the tolerance)
+  if (h->crt_h && h->crt.n_mod >= kCrtMinModuliRR) {
     GemmArgs g = gargs(n, k, n, H, ldh, Q, ldq, P, n);
     g.gamma = 0.0;
     g.beta = 0.0;

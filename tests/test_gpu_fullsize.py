@@ -110,3 +110,27 @@ def test_solve_full_size_properties(problem, prec):
     for a in (0, 1, 499, 998, 999):
         r = Hh @ vh[:, a] - ev[a] * vh[:, a]
         assert np.linalg.norm(r) <= 1e-10 * max(abs(st["b_sup"]), abs(st["mu_1"]), norm) * 1.01
+
+
+@pytest.mark.parametrize("moduli", [12, 14])
+def test_solve_int8_products_residuals_confirmed(problem, moduli):
+    """Two-term split-BF16 with the FP64 products on INT8: every returned
+    residual recomputed without the library (torch's GEMM on the stored H)
+    meets the tolerance.  With 12 moduli only the filter runs on INT8 (the
+    Rayleigh-Ritz product that the reported residuals come from stays on the
+    FP64 cores: on INT8 with 12 moduli it let 1.4e-10 pass as 9.8e-11)."""
+    import torch
+    pk, prob = problem
+    announce(f"full-size solve n={N} bf16x2 with FP64 products on INT8, {moduli} moduli")
+    opts = pk.default_opts(filter_prec=pk.PREC_BF16X2, fp64_emulation=moduli)
+    ev, vec, res, st = pk.chase_solve(prob["H"], NEV, NEX, 1e-10, 20, prob["V0"], prob["S"],
+                                      opts=opts)
+    assert st["converged"] and np.all(res <= 1e-10)
+    lam = prob["lam"]
+    norm = max(abs(lam[0]), abs(lam[-1]))
+    assert np.max(np.abs(ev - lam[:NEV])) <= 2e-10 * norm
+    lam_t = torch.tensor(ev, dtype=torch.float64, device=vec.device)
+    v = vec.contiguous()
+    rn = torch.linalg.vector_norm(prob["H"] @ v - v * lam_t[None, :], dim=0).cpu().numpy()
+    scale = max(abs(st["b_sup"]), abs(st["mu_1"]), norm)
+    assert np.all(rn <= 1e-10 * scale * 1.01), rn.max() / scale
