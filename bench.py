@@ -498,7 +498,7 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
                                        "t_resid")},
             qr_shifted=st["qr_shifted"], qr_householder=st["qr_householder"],
             eig_jacobi_calls=st["eig_jacobi_calls"], eig_jacobi_sweeps=st["eig_jacobi_sweeps"],
-            stats=st, evals=ev)
+            steps=steps, warmup=warmup, stats=st, evals=ev)
         if warm_start:
             results[prec]["warm_start"] = warm_start_step(pk, H, vec, V0, S, nev, nex, wl, norm,
                                                           handle)
@@ -510,7 +510,8 @@ def time_modes(pk, prob, wl, precs, steps, warmup, label, verbose=False, max_deg
 
 MODE_KEYS = ("solve_s", "converged", "max_resid", "max_eig_err_rel", "max_resid_independent",
              "iterations", "matvecs_fp64", "matvecs_low", "fp64_tail", "filter_tflops", "phases",
-             "qr_shifted", "qr_householder", "eig_jacobi_calls", "eig_jacobi_sweeps")
+             "qr_shifted", "qr_householder", "eig_jacobi_calls", "eig_jacobi_sweeps", "steps",
+             "warmup")
 
 
 def mode_summary(m, prec, fp64_solve_s):
@@ -698,6 +699,9 @@ def main():
                     help="skip the vendor GEMM rates printed beside the roofline")
     ap.add_argument("--library-reference", action="store_true",
                     help="only time the vendor GEMMs (torch -> hipBLASLt / rocBLAS)")
+    ap.add_argument("--extra-steps", type=int, default=5,
+                    help="timed solves of each mode other than the main (FP64) one at most "
+                         "(warm-ups at most 2)")
     ap.add_argument("--mixed-extra", nargs="*", default=[], choices=["fp64i8"],
                     help="further modes for the n=30000 block (fp64i8: every FP64 product "
                          "on INT8, about 40 s more)")
@@ -800,8 +804,16 @@ def main():
     precs = {"both": ["fp64", "fp32"],
              "all": ["fp64", "fp32", "bf16x3", "bf16x2", "fp64i8", "bf16x2i8"],
              "int8": ["fp64", "fp64i8", "bf16x2", "bf16x2i8"]}.get(args.prec, [args.prec])
-    results = time_modes(pk, prob, wl, precs, args.steps, args.warmup, args.workload,
+    # the main mode takes the requested steps; the other modes, reported
+    # beside it, at most --extra-steps (their rates settle within a few solves)
+    main_first = "fp64" if "fp64" in precs else precs[0]
+    results = time_modes(pk, prob, wl, [main_first], args.steps, args.warmup, args.workload,
                          verbose=args.verbose, max_deg=args.max_deg, warm_start=args.warm_start)
+    rest = [p for p in precs if p != main_first]
+    if rest:
+        results.update(time_modes(pk, prob, wl, rest, min(args.steps, args.extra_steps),
+                                  min(args.warmup, 2), args.workload, verbose=args.verbose,
+                                  max_deg=args.max_deg, warm_start=args.warm_start))
     H = prob["H"]
 
     main_prec = "fp64" if "fp64" in results else precs[0]
