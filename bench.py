@@ -574,6 +574,63 @@ def eigensolver_block(pk, k, reps=2):
     return out
 
 
+def cholesky_block(pk, k, reps=10):
+    """The Cholesky factor of the QR step's Cholesky passes on its own
+    (chase_cholesky) on B^H B, B a seeded (2k + 8) x k Gaussian block,
+    complex and real: the library's kernels timed with HIP events on the
+    stream they run on (median of `reps` calls after two untimed ones, the
+    matrix restored before each), torch.linalg.cholesky on the same matrix
+    timed the same way, and the backward error max|R^H R - A| / max|A|."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    L = pk.lib()
+    out = {"k": k, "cases": {}}
+    for dt, name in ((torch.complex128, "c128"), (torch.float64, "f64")):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(k)
+        b = torch.randn((2 * k + 8, k), dtype=dt, device="cuda", generator=g)
+        a0 = (b.mH @ b).contiguous()
+        del b
+        buf = torch.empty_like(a0)
+        h = pk.Handle(2, 1, 1, dt)
+        info = ctypes.c_int()
+
+        def timed(fn):
+            ts = []
+            for r in range(reps + 2):
+                buf.copy_(a0)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                if r >= 2:
+                    ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts))
+
+        def lib_call():
+            rc = L.chase_cholesky(h.ptr, ctypes.c_void_p(buf.data_ptr()), k, k,
+                                  ctypes.byref(info), pk._stream())
+            if rc != 0 or info.value != 0:
+                raise RuntimeError(f"chase_cholesky: status {rc}, info {info.value}")
+
+        lib_ms = timed(lib_call)
+        # buf (row-major) is the column-major A^T = conj(A); R^H R = conj(A) there
+        R = torch.triu(buf.transpose(0, 1))
+        err = ((R.mH @ R - a0.transpose(0, 1)).abs().max() / a0.abs().max()).item()
+        torch_ms = timed(lambda: torch.linalg.cholesky(buf, upper=True))
+        h.close()
+        row = {"library_ms": lib_ms, "torch_linalg_cholesky_ms": torch_ms,
+               "speedup": torch_ms / lib_ms, "backward_err": err}
+        out["cases"][name] = row
+        log(f"cholesky k={k} {name}: {row}")
+    return out
+
+
 def library_gemm_reference():
     """Rates of the vendor's own GEMMs on this GPU (torch -> hipBLASLt /
     rocBLAS), timed the same way as the library's kernels, as the practical
@@ -722,6 +779,9 @@ def main():
     ap.add_argument("--eigensolver", type=int, default=None, metavar="K",
                     help="only time the Rayleigh-Ritz eigensolve (Jacobi and rocSOLVER) "
                          "on K x K complex Hermitian matrices")
+    ap.add_argument("--cholesky", type=int, default=None, metavar="K",
+                    help="only time the QR passes' Cholesky factorisation (the library's "
+                         "and torch.linalg.cholesky) on K x K positive definite matrices")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--max-deg", type=int, default=None,
                     help="cap of the optimised filter degree (library default 36)")
@@ -745,6 +805,10 @@ def main():
     if args.eigensolver is not None:
         import paper_2205_02491_amd as pk
         print(json.dumps(eigensolver_block(pk, args.eigensolver)), flush=True)
+        return
+    if args.cholesky is not None:
+        import paper_2205_02491_amd as pk
+        print(json.dumps(cholesky_block(pk, args.cholesky)), flush=True)
         return
     if args.calib_copy:
         import torch

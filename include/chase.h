@@ -338,6 +338,21 @@ chase_status chase_heev(chase_handle_t handle, void* G_dev, int64_t ldg, int k,
                         int method, double* evals_host, int* sweeps_host,
                         void* stream);
 
+/* Cholesky factorisation A = R^H R of a Hermitian positive definite matrix,
+ * the factorisation inside chase_qr's Cholesky QR passes (this library's
+ * reading of the QR step of Algorithm 1; Section 2.3 names Householder QR)
+ * on its own.  A_dev (k x k, ld lda >= max(1, k), column-major, the handle's
+ * element type): its upper triangle is read and overwritten by R (upper
+ * triangular, positive real diagonal); the strict lower triangle is not
+ * touched.  info_host receives 0, or the 1-based order of the first
+ * leading minor that is not positive definite, as LAPACK's potrf; then A
+ * holds partial results (not an error status: CHASE_OK is returned).
+ * Non-finite pivots count as not positive.  k = 0 is a no-op (A_dev may
+ * then be NULL).  Needs no workspace and allocates nothing; k is not
+ * limited by the handle's sizes. */
+chase_status chase_cholesky(chase_handle_t handle, void* A_dev, int64_t lda, int k,
+                            int* info_host, void* stream);
+
 /* Adjoint of the eigenvalue map: dH += V diag(g) V^H for V_dev (n x m,
  * ld ldv) orthonormal eigenvectors and g_host[m]; dH_dev (n x n, ld ldd)
  * is accumulated into (the gradient of sum_i g_i lambda_i w.r.t. Hermitian

@@ -30,7 +30,8 @@ _STATUS = {1: "CHASE_ERR_ARG", 2: "CHASE_ERR_NOMEM", 3: "CHASE_ERR_HIP",
 EXPORTED = ["chase_default_opts", "chase_workspace_bytes", "chase_create", "chase_destroy",
             "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
             "chase_filter_ritz", "chase_qr",
-            "chase_rayleigh_ritz", "chase_heev", "chase_eigval_adjoint", "chase_eigvec_adjoint",
+            "chase_rayleigh_ritz", "chase_heev", "chase_cholesky", "chase_eigval_adjoint",
+            "chase_eigvec_adjoint",
             "chase_filter_adjoint", "chase_filter_coefficients", "chase_spectral_bounds",
             "chase_degrees", "chase_last_error"]
 
@@ -115,6 +116,8 @@ def lib():
     L.chase_rayleigh_ritz.restype = ci
     L.chase_heev.argtypes = [vp, vp, i64, ci, ci, pd, pi, vp]
     L.chase_heev.restype = ci
+    L.chase_cholesky.argtypes = [vp, vp, i64, ci, pi, vp]
+    L.chase_cholesky.restype = ci
     L.chase_eigval_adjoint.argtypes = [vp, vp, i64, ci, pd, vp, i64, vp]
     L.chase_eigval_adjoint.restype = ci
     L.chase_filter_adjoint.argtypes = [vp, vp, i64, vp, i64, vp, i64, vp, vp]
@@ -482,6 +485,29 @@ def chase_heev(G, method=EIG_AUTO, handle=None):
     return ev, buf.mH, sw.value
 
 
+def chase_cholesky(A, handle=None):
+    """Cholesky factor A = R^H R of the Hermitian positive definite A (k x k)
+    with the factorisation of the library's Cholesky QR passes.  Returns
+    (R tensor (k, k) upper triangular, info): info is 0, or the 1-based
+    order of the first leading minor that is not positive definite (then R
+    is partial).  A is not modified."""
+    import torch
+    _check_square(A)
+    k = A.shape[0]
+    if handle is None:
+        handle = Handle(2, 1, 1, A.dtype)
+    if handle.cplx != (A.dtype == torch.complex128):
+        raise ValueError("handle and A differ in element type")
+    # a row-major copy of A^T is A in column-major order (the library reads
+    # the upper triangle of A itself)
+    buf = A.transpose(0, 1).resolve_conj().clone(memory_format=torch.contiguous_format)
+    info = ctypes.c_int()
+    _check(lib().chase_cholesky(handle.ptr, _dev(buf), max(1, k), k, ctypes.byref(info),
+                                _stream()))
+    # buf^T is the column-major result: R over A's upper triangle
+    return torch.triu(buf.transpose(0, 1)), info.value
+
+
 def chase_eigval_adjoint(V, g, dH, handle=None):
     """dH += V diag(g) V^H (in place on the torch tensor dH, n x n)."""
     if V.dim() != 2:
@@ -597,7 +623,7 @@ from .autograd import ChaseEigh, chase_eigh, filtered_block  # noqa: E402
 __all__ = ["Handle", "Opts", "Stats", "ChaseError", "default_opts", "chase_workspace_bytes",
            "chase_solve", "chase_lanczos", "chase_lanczos_noalloc", "chase_filter",
            "chase_filter_ritz", "chase_qr",
-           "chase_rayleigh_ritz", "chase_heev",
+           "chase_rayleigh_ritz", "chase_heev", "chase_cholesky",
            "chase_eigval_adjoint", "chase_eigvec_adjoint", "chase_filter_adjoint",
            "chase_filter_coefficients", "chase_spectral_bounds", "chase_degrees", "ChaseEigh",
            "chase_eigh",

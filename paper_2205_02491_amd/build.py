@@ -16,8 +16,8 @@ OUT = os.path.join(PKG, "libchase.so")
 ARCH = os.environ.get("CHASE_OFFLOAD_ARCH", "gfx950")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "kernels.hip", "eigh.hip", "crt.hip", "solver.hip",
-           "hostmath.cpp"]
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "kernels.hip", "eigh.hip", "crt.hip", "chol.hip",
+           "solver.hip", "hostmath.cpp"]
 
 HIPFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -240,6 +240,13 @@ void crt_prepare_h(bool cplx, const void* H, int64_t ldh, int64_t n, const CrtBa
 void crt_cheb(bool cplx, const GemmArgs& g, const CrtBasis& B, const void* hbuf, void* xbuf,
               int kmax, rocblas_handle rb, hipStream_t st);
 
+// ------------------------------------------------------------------ Cholesky
+// A = R^H R for the Hermitian positive definite k x k matrix A (ld lda,
+// upper triangle read and overwritten by R; the strict lower triangle is
+// left alone).  d_info (device) receives 0, or the 1-based order of the
+// first pivot that is not positive (then A holds partial results).
+void cholesky_upper(bool cplx, void* A, int64_t lda, int k, int* d_info, hipStream_t st);
+
 // ------------------------------------------------------------------ Jacobi eigensolver
 // Device workspace of the block Jacobi eigensolver for orders up to kmax.
 size_t jacobi_ws_bytes(bool cplx, int kmax);

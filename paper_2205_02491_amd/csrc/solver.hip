@@ -580,15 +580,8 @@ void householder_qr(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void*
   if (bad) throw Error(CHASE_ERR_NUMERIC, "QR breakdown (non-finite values)");
 }
 
-void potrf(chase_handle_s* h, void* R, int64_t ldr, int k) {
-  if (h->cplx)
-    rb_check(rocsolver_zpotrf(h->rb, rocblas_fill_upper, k,
-                              static_cast<rocblas_double_complex*>(R), ldr, h->d_info),
-             "zpotrf");
-  else
-    rb_check(rocsolver_dpotrf(h->rb, rocblas_fill_upper, k, static_cast<double*>(R), ldr,
-                              h->d_info),
-             "dpotrf");
+void potrf(chase_handle_s* h, void* R, int64_t ldr, int k, hipStream_t st) {
+  cholesky_upper(h->cplx, R, ldr, k, h->d_info, st);
 }
 
 void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, chase_stats* stats,
@@ -619,7 +612,7 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
     gram_scale(cplx, R, ldr, k, 0.0, h->d_scale, h->d_flags, st);
     // keep the scaled Gram matrix in case the pass has to be shifted
     copy_cols(cplx, R, ldr, h->G, ldr, k, k, st);
-    potrf(h, R, ldr, k);
+    potrf(h, R, ldr, k, st);
     sync_info(true);
     if (hinfo[1] != 0) return householder_qr(h, X, ldx, k, L, Wb, stats, st);
     double dmin = INFINITY;
@@ -631,7 +624,7 @@ void qr_step(chase_handle_s* h, void* X, int64_t ldx, int k, int L, void* Wb, ch
       // shifted pass on the saved Gram matrix
       copy_cols(cplx, h->G, ldr, R, ldr, k, k, st);
       add_diag(cplx, R, ldr, k, shift, st);
-      potrf(h, R, ldr, k);
+      potrf(h, R, ldr, k, st);
       sync_info(false);
       if (hinfo[0] != 0) return householder_qr(h, X, ldx, k, L, Wb, stats, st);
       ++shifted;
@@ -1566,6 +1559,21 @@ chase_status chase_heev(chase_handle_t h, void* G, int64_t ldg, int k, int metho
     CHASE_HIP(hipMemcpyAsync(evals, h->d_evals, k * 8, hipMemcpyDeviceToHost, st));
     CHASE_HIP(hipStreamSynchronize(st));
     if (sweeps) *sweeps = sw < 0 ? 0 : sw;
+  });
+}
+
+chase_status chase_cholesky(chase_handle_t h, void* A, int64_t lda, int k, int* info,
+                            void* stream) {
+  return guarded([&] {
+    CHASE_REQUIRE(h != nullptr, "handle is NULL");
+    CHASE_REQUIRE(info && (A || k == 0), "NULL pointer argument");
+    CHASE_REQUIRE(k >= 0, "k must be non-negative");
+    CHASE_REQUIRE(lda >= std::max(1, k), "leading dimension smaller than k");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    set_stream(h, st);
+    cholesky_upper(h->cplx, A, lda, k, h->d_info, st);
+    CHASE_HIP(hipMemcpyAsync(info, h->d_info, sizeof(int), hipMemcpyDeviceToHost, st));
+    CHASE_HIP(hipStreamSynchronize(st));
   });
 }
 

@@ -14,7 +14,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2205_02491_amd", "csrc")
 HIPCC = os.path.join(os.environ.get("ROCM_PATH", "/opt/rocm"), "bin", "hipcc")
-SOURCES = ["gemm.hip", "gemm_bf16.hip", "kernels.hip", "eigh.hip", "crt.hip", "solver.hip"]
+SOURCES = ["gemm.hip", "gemm_bf16.hip", "kernels.hip", "eigh.hip", "crt.hip", "chol.hip",
+           "solver.hip"]
 
 
 def _resources(src):
