@@ -35,12 +35,14 @@ def _problem(n, cplx, seed, row_scale=False):
 
 @pytest.mark.parametrize("cplx", [True, False])
 @pytest.mark.parametrize("n,k,nm", [(300, 37, 14), (700, 150, 14), (1000, 140, 16),
-                                    (1000, 140, 12), (333, 17, 14), (515, 64, 16)])
+                                    (1000, 140, 12), (333, 17, 14), (515, 64, 16),
+                                    (40, 2, 14), (129, 5, 16)])
 def test_int8_filter_matches_oracle(pk, cplx, n, k, nm):
     import torch
     announce(f"INT8 CRT filter n={n} k={k} moduli={nm} cplx={cplx}")
-    # n = 333 and 515 (not multiples of 4) take the one-entry-per-thread
-    # conversion and reconstruction kernels, the others the four-wide ones
+    # n = 333, 515 and 129 (not multiples of 4) take the one-entry-per-thread
+    # conversion and reconstruction kernels, the others the four-wide ones;
+    # (40, 2) and (129, 5) are the smallest blocks a handle takes
     h, g = _problem(n, cplx, 2000 + n + k + nm)
     x = gen.gaussian(g, (n, k), cplx)
     # columns of very different size (each column gets its own scale)
