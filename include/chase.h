@@ -148,7 +148,9 @@ typedef struct chase_opts {
                           from which the reported residuals come, runs on
                           INT8 only with 14 or 16 moduli (with 12 the
                           residuals were off by half of tol = 1e-10); fewer
-                          moduli serve the filter alone.  H must be
+                          moduli serve the filter alone, for looser
+                          tolerances: with 12 the n = 20000 solve stalls at a
+                          residual near 1e-10.  H must be
                           Hermitian and n <= 65535; the handle keeps 3N n^2
                           bytes of residues of H (complex; N n^2 real) and
                           15N n (nev+nex) bytes of per-step buffers         */
